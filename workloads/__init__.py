@@ -1,0 +1,231 @@
+"""Seeded synthetic inputs for the dynamic max-flow workloads.
+
+This module is shared test/benchmark infrastructure. Both the CPU oracle side and
+the GPU side draw their inputs from it, so it deliberately holds none of the
+max-flow arithmetic: it only draws directed graphs (as CSR arrays), integer
+capacities and update batches from seeded numpy generators.
+
+Conventions
+-----------
+* A graph is returned as ``Graph(n, row_ptr, col, cap, s, t)``: ``row_ptr`` is
+  int64[n+1], ``col`` int32[m] and ``cap`` int32[m]. Edge ``i`` is the CSR
+  position ``i``; its tail is the row that holds it. Within a row, edges are
+  sorted by head (stable, so duplicates keep their draw order).
+* A batch is ``(edge_ids int64[k], new_caps int32[k])`` of *distinct* edge ids
+  with absolute new capacities (a batch is a set of edges with new capacities,
+  Sec. 4 of the paper). The first ceil(k/2) entries raise the capacity, the
+  rest lower it (new value uniform in [0, c]), as in the mixed experiments
+  (Sec. 6.4).
+* Seeds: workload ``i`` uses ``SEED_BASE + i``; batch ``j`` of a chain uses the
+  seed sequence ``[seed, j]``.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+
+SEED_BASE = 251105895
+
+
+@dataclass
+class Graph:
+    n: int
+    row_ptr: np.ndarray  # int64[n+1]
+    col: np.ndarray      # int32[m]
+    cap: np.ndarray      # int32[m]
+    s: int
+    t: int
+
+    @property
+    def m(self) -> int:
+        return int(self.col.shape[0])
+
+    def tails(self) -> np.ndarray:
+        """int32[m]: tail vertex of every edge (expanded from row_ptr)."""
+        deg = np.diff(self.row_ptr)
+        return np.repeat(np.arange(self.n, dtype=np.int32), deg)
+
+
+def rng_for(seed, *stream) -> np.random.Generator:
+    return np.random.default_rng(np.random.SeedSequence([int(seed), *[int(x) for x in stream]]))
+
+
+def edges_to_csr(n: int, src: np.ndarray, dst: np.ndarray, cap: np.ndarray,
+                 s: int, t: int) -> Graph:
+    """Sort an edge list by (tail, head), stable, into CSR arrays."""
+    src = np.asarray(src, dtype=np.int64)
+    dst = np.asarray(dst, dtype=np.int64)
+    key = src * np.int64(n) + dst
+    order = np.argsort(key, kind="stable")
+    src_s = src[order]
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(np.bincount(src_s, minlength=n), out=row_ptr[1:])
+    return Graph(n, row_ptr, dst[order].astype(np.int32),
+                 np.asarray(cap)[order].astype(np.int32), int(s), int(t))
+
+
+# --------------------------------------------------------------------------
+# Uniform random directed graph (small parity workload)
+# --------------------------------------------------------------------------
+
+def random_graph(n: int, m: int, cap_lo: int, cap_hi: int, seed, s: int = 0,
+                 t: int | None = None, allow_self_loops: bool = False) -> Graph:
+    """Uniform endpoints; self-loops redrawn unless allowed; duplicates and
+    antiparallel pairs kept. Capacities uniform in [cap_lo, cap_hi]."""
+    rng = rng_for(seed, 0)
+    src = rng.integers(0, n, m, dtype=np.int64)
+    dst = rng.integers(0, n, m, dtype=np.int64)
+    if not allow_self_loops and n > 1:
+        bad = src == dst
+        while bad.any():
+            dst[bad] = rng.integers(0, n, int(bad.sum()), dtype=np.int64)
+            bad = src == dst
+    cap = rng.integers(cap_lo, cap_hi + 1, m, dtype=np.int64)
+    return edges_to_csr(n, src, dst, cap, s, n - 1 if t is None else t)
+
+
+def c1_random_1k(seed=SEED_BASE + 0) -> Graph:
+    """1,000 vertices, 8,000 edges, capacities U[1,100], s=0, t=999."""
+    return random_graph(1000, 8000, 1, 100, seed, s=0, t=999)
+
+
+# --------------------------------------------------------------------------
+# Image-segmentation grid
+# --------------------------------------------------------------------------
+
+def _blurred_intensity(side: int, blur_sigma: float, rng: np.random.Generator) -> np.ndarray:
+    from scipy.ndimage import gaussian_filter
+    noise = rng.standard_normal((side, side))
+    img = gaussian_filter(noise, sigma=blur_sigma, mode="reflect", truncate=3.0)
+    lo, hi = float(img.min()), float(img.max())
+    return (img - lo) / (hi - lo) if hi > lo else np.zeros_like(img)
+
+
+def seg_grid(side: int, seed, sigma: float = 0.1, blur_sigma: float = 2.0,
+             tlink_hi: int = 200, nlink_scale: int = 100, tlink_lo: int = 0) -> Graph:
+    """4-connected side x side grid, pixels row-major 0..side^2-1, s = side^2,
+    t = side^2+1. Both directions of each neighbour pair carry
+    1 + round(scale * exp(-(I_p - I_q)^2 / (2 sigma^2))); every pixel has
+    s->p and p->t with independent U[tlink_lo, tlink_hi] capacities."""
+    rng = rng_for(seed, 0)
+    img = _blurred_intensity(side, blur_sigma, rng)
+    npx = side * side
+    s, t = npx, npx + 1
+    idx = np.arange(npx, dtype=np.int64).reshape(side, side)
+    # horizontal and vertical neighbour pairs
+    pa = np.concatenate([idx[:, :-1].ravel(), idx[:-1, :].ravel()])
+    pb = np.concatenate([idx[:, 1:].ravel(), idx[1:, :].ravel()])
+    ia = img.ravel()[pa]
+    ib = img.ravel()[pb]
+    w = 1 + np.floor(nlink_scale * np.exp(-((ia - ib) ** 2) / (2.0 * sigma * sigma)) + 0.5)
+    w = w.astype(np.int64)
+    src = np.concatenate([pa, pb, np.full(npx, s, np.int64), np.arange(npx, dtype=np.int64)])
+    dst = np.concatenate([pb, pa, np.arange(npx, dtype=np.int64), np.full(npx, t, np.int64)])
+    tl = rng.integers(tlink_lo, tlink_hi + 1, 2 * npx, dtype=np.int64)
+    cap = np.concatenate([w, w, tl])
+    return edges_to_csr(npx + 2, src, dst, cap, s, t)
+
+
+def c2_grid_512(seed=SEED_BASE + 1) -> Graph:
+    return seg_grid(512, seed)
+
+
+# --------------------------------------------------------------------------
+# R-MAT power-law graph
+# --------------------------------------------------------------------------
+
+def rmat(scale: int, edge_factor: int, seed, a=0.57, b=0.19, c=0.19,
+         cap_lo: int = 1, cap_hi: int = 1000, permute: bool = True,
+         chunk: int = 1 << 22) -> Graph:
+    """R-MAT(a,b,c,d) with 2^scale vertices and edge_factor*2^scale edges.
+    Self-loops are redrawn, duplicates kept as separate edges, vertex ids
+    randomly permuted. s / t = highest / second-highest total degree (ties to
+    the lower id). Capacities U[cap_lo, cap_hi]."""
+    n = 1 << scale
+    m = edge_factor * n
+    rng = rng_for(seed, 0)
+
+    def draw(cnt: int):
+        u = np.zeros(cnt, dtype=np.int64)
+        v = np.zeros(cnt, dtype=np.int64)
+        for lvl in range(scale):
+            r = rng.random(cnt)
+            ubit = r >= (a + b)
+            vbit = ((r >= a) & (r < a + b)) | (r >= (a + b + c))
+            u |= ubit.astype(np.int64) << lvl
+            v |= vbit.astype(np.int64) << lvl
+        return u, v
+
+    src = np.empty(m, dtype=np.int64)
+    dst = np.empty(m, dtype=np.int64)
+    for lo in range(0, m, chunk):
+        hi = min(m, lo + chunk)
+        u, v = draw(hi - lo)
+        src[lo:hi] = u
+        dst[lo:hi] = v
+    bad = np.nonzero(src == dst)[0]
+    while bad.size:
+        u, v = draw(bad.size)
+        src[bad] = u
+        dst[bad] = v
+        bad = bad[u == v]
+    if permute:
+        perm = rng.permutation(n).astype(np.int64)
+        src = perm[src]
+        dst = perm[dst]
+    cap = rng.integers(cap_lo, cap_hi + 1, m, dtype=np.int64)
+    deg = np.bincount(src, minlength=n) + np.bincount(dst, minlength=n)
+    order = np.lexsort((np.arange(n), -deg))  # highest degree first, ties -> lower id
+    s, t = int(order[0]), int(order[1])
+    return edges_to_csr(n, src, dst, cap, s, t)
+
+
+def c3_rmat20(seed=SEED_BASE + 2) -> Graph:
+    return rmat(20, 16, seed)
+
+
+# --------------------------------------------------------------------------
+# Update batches
+# --------------------------------------------------------------------------
+
+def batch_size(m: int, fraction: float) -> int:
+    return max(1, int(round(m * fraction)))
+
+
+def mixed_batch(cur_cap: np.ndarray, k: int, inc_hi: int, rng: np.random.Generator,
+                inc_fraction: float = 0.5, ids: np.ndarray | None = None):
+    """k distinct edges; the first ceil(k*inc_fraction) get cap + U[1, inc_hi],
+    the rest a new capacity U[0, cap]."""
+    m = int(cur_cap.shape[0])
+    k = min(int(k), m)
+    if ids is None:
+        ids = rng.choice(m, size=k, replace=False).astype(np.int64)
+    else:
+        ids = np.asarray(ids, dtype=np.int64)
+    n_inc = int(math.ceil(k * inc_fraction))
+    cur = cur_cap[ids].astype(np.int64)
+    new = np.empty(k, dtype=np.int64)
+    new[:n_inc] = cur[:n_inc] + rng.integers(1, inc_hi + 1, n_inc, dtype=np.int64)
+    new[n_inc:] = rng.integers(0, cur[n_inc:] + 1, dtype=np.int64)
+    return ids, new.astype(np.int32)
+
+
+def batch_chain(g: Graph, fraction: float, count: int, inc_hi: int, seed,
+                inc_fraction: float = 0.5, k: int | None = None):
+    """Yield `count` successive batches (ids, new_caps); capacities evolve as
+    each batch is applied, so batch j is drawn against the capacities that
+    batches 0..j-1 left behind."""
+    cur = g.cap.copy()
+    kk = batch_size(g.m, fraction) if k is None else int(k)
+    for j in range(count):
+        ids, new = mixed_batch(cur, kk, inc_hi, rng_for(seed, 1, j), inc_fraction)
+        cur[ids] = new
+        yield ids, new
+
+
+def apply_batch(cap: np.ndarray, ids: np.ndarray, new: np.ndarray) -> np.ndarray:
+    out = cap.copy()
+    out[ids] = new
+    return out
