@@ -1,0 +1,210 @@
+/*
+ * mf.h - exact maximum flow / minimum cut on one AMD Instinct MI355X (gfx950),
+ * static and after batches of edge-capacity changes.
+ *
+ * The method is the GPU push-relabel of Kannappan, Kumar and Nasre,
+ * "Efficient Dynamic MaxFlow Computation on GPUs" (arXiv 2511.05895):
+ * the static solve of Sec. 3 (Alg. 1-3) and the Dynamic Push Relabel of
+ * Sec. 4.1 (Alg. 4-5), run data-driven (Sec. 5.3) or topology-driven
+ * (Sec. 5.2) on a bi-directional CSR (Sec. 5.1).
+ *
+ * Conventions for every call
+ *  - Every call returns an int status: MF_OK (0) or one of the MF_E* codes.
+ *    mf_last_error() gives the text of the last failure on that handle.
+ *  - Host pointers are read (or written) only during the call; the library
+ *    never keeps them.  Pointers documented as "device" must be addresses in
+ *    the handle's device memory space (e.g. from hipMalloc or a torch CUDA
+ *    tensor) and are read on the handle's stream during the call.
+ *  - Calls are synchronous: when one returns, its GPU work has finished.
+ *  - A handle is not thread-safe; distinct handles are independent.
+ *  - No C++ exception crosses this interface.
+ *  - Integer sizes: capacities int32 (each edge in [0, limit], limit <= 2^30,
+ *    see mf_cap_limit), excesses and flow values int64, vertex ids int32,
+ *    edge ids int64 in [0, m) (m < 2^31), merged arcs < 2^31.
+ */
+#ifndef MF_H
+#define MF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MF_API __attribute__((visibility("default")))
+
+/* status codes */
+#define MF_OK 0
+#define MF_EINVAL 1   /* bad argument; the handle is unchanged               */
+#define MF_ENOMEM 2   /* device or host allocation failed                    */
+#define MF_EDEVICE 3  /* HIP runtime error or device-side abort              */
+#define MF_ESTATE 4   /* call not allowed in the handle's current state      */
+#define MF_ETIMEOUT 5 /* iteration limit reached before the loop converged   */
+
+/* work distribution of the push/relabel and invalid-edge sweeps */
+#define MF_MODE_DATA 0     /* worklist of active vertices (Sec. 5.3)          */
+#define MF_MODE_TOPOLOGY 1 /* every vertex, idle when inactive (Sec. 5.2)     */
+
+typedef struct mf_handle mf_handle_t;
+
+/* Directed input graph in CSR form.  Edge id i is CSR position i; its tail is
+ * the row v with row_ptr[v] <= i < row_ptr[v+1], its head col[i].  Duplicate
+ * edges, antiparallel edges and self-loops are allowed (Sec. 2.1 places no
+ * restriction on E).  row_ptr: int64[n+1], col: int32[m]. */
+typedef struct {
+    int32_t n;
+    int64_t m;
+    const int64_t *row_ptr;
+    const int32_t *col;
+} mf_csr_t;
+
+typedef struct {
+    int32_t kernel_cycles;  /* KERNELCYCLES of Alg. 2: push/relabel attempts per
+                               active vertex per sweep; 0 = max(1, round(m/n)),
+                               the average degree used in Sec. 6.1          */
+    int32_t mode;           /* MF_MODE_DATA (default) or MF_MODE_TOPOLOGY     */
+    int32_t grid_blocks;    /* workgroups of the persistent solve kernel;
+                               0 = chosen from the graph size; 1 = one
+                               workgroup (no grid-wide barrier)              */
+    int32_t device;         /* HIP device ordinal (default 0)                 */
+    int64_t max_iterations; /* loop rounds (global relabel + sweeps) allowed
+                               per call; < 0 unlimited (default)            */
+    int32_t time_budget_ms; /* wall time one solve launch may take before it
+                               stops with MF_ETIMEOUT (resumable); 0 = 60 s */
+    int32_t reserved[7];    /* must be zero                                   */
+} mf_opts_t;
+
+/* Counters of the last mf_solve / mf_apply_updates* / mf_resume call. */
+typedef struct {
+    int64_t iterations;       /* loop rounds that ran push/relabel            */
+    int64_t global_relabels;  /* backward BFS passes                          */
+    int64_t bfs_levels;       /* BFS levels expanded, summed over passes      */
+    int64_t bfs_vertices;     /* vertices given a height by the BFS (roots too) */
+    int64_t bfs_arcs;         /* arcs examined by the BFS                     */
+    int64_t pr_vertex_cycles; /* push/relabel cycles run on active vertices   */
+    int64_t pr_arcs;          /* arcs scanned by push/relabel                 */
+    int64_t pushes;
+    int64_t relabels;
+    int64_t rie_arcs;         /* arcs scanned by RemoveInvalidEdges           */
+    int64_t rie_saturations;
+    int64_t updates;          /* edge updates applied                         */
+    int64_t clamps;           /* arcs whose flow was clamped to a new capacity */
+    int64_t source_pushes;    /* arcs out of s saturated                      */
+    int64_t loop_launches;    /* launches of the persistent solve kernel      */
+    int64_t grid_blocks;      /* workgroups of that kernel                    */
+    double loop_kernel_ms;    /* HIP-event time of the solve kernel launches  */
+    double call_ms;           /* HIP-event time of the whole call's GPU work  */
+} mf_stats_t;
+
+/* Fill *opts with the defaults described above. */
+MF_API void mf_default_opts(mf_opts_t *opts);
+
+/* Create a handle for graph g with per-edge capacities cap (int32[m], host),
+ * source s and sink t (Sec. 2.1).  Builds the bi-directional CSR of Sec. 5.1:
+ * all input edges between one unordered vertex pair become ONE arc pair (the
+ * residual c_f(u,v) = c(u,v) - f(u,v) + f(v,u) of Sec. 2.3 is per vertex pair),
+ * arcs of a vertex sorted by neighbour id; self-loops get no arc.  Uploads it
+ * to device memory owned by the handle.  Does not solve.
+ * opts may be NULL (defaults).  *out receives the handle.
+ * Errors: MF_EINVAL (n < 2, m < 0 or m >= 2^31, s == t, s/t/col out of range,
+ * row_ptr not non-decreasing from 0 to m, a capacity < 0 or above the limit
+ * of mf_cap_limit, opts out of range), MF_ENOMEM, MF_EDEVICE. */
+MF_API int mf_create(const mf_csr_t *g, const int32_t *cap, int32_t s, int32_t t,
+                     const mf_opts_t *opts, mf_handle_t **out);
+
+/* Free the handle and its device memory.  NULL is ignored. */
+MF_API void mf_destroy(mf_handle_t *h);
+
+/* Text of the last error on h (or of the last failed mf_create when h is
+ * NULL).  Owned by the library; valid until the next call on h. */
+MF_API const char *mf_last_error(const mf_handle_t *h);
+
+/* Static solve from scratch on the current capacities (Alg. 1): reset the
+ * flow, saturate the arcs out of s, then loop {global relabel; stop if no
+ * active vertex; PushRelabel (Alg. 2); RemoveInvalidEdges (Alg. 3)}.
+ * Every deficient vertex is a BFS root too (as in Alg. 4), so the value is
+ * exact even when RemoveInvalidEdges leaves deficits.
+ * Errors: MF_ETIMEOUT (max_iterations or the time budget reached; the state
+ * is a valid intermediate state that mf_resume continues), MF_EDEVICE. */
+MF_API int mf_solve(mf_handle_t *h);
+
+/* Dynamic update (Alg. 4 with Alg. 5): set edge_ids[i] to the absolute
+ * capacity new_caps[i] (host arrays, k entries, a SET of distinct edge ids:
+ * Sec. 4 defines a batch as a set).  Capacity 0 removes an edge, 0 -> c > 0
+ * adds one (Sec. 4.1).  Applies the capacity deltas to c and c_f, clamps the
+ * flow of every arc whose residual became negative (booking the returned
+ * flow as excess at its tail and deficit at its head), pushes any residual
+ * capacity left on arcs out of s, and resumes the loop from the previous
+ * state with deficient vertices as extra sinks.
+ * Requires a solved handle (MF_ESTATE otherwise).  k == 0 is allowed.
+ * Errors: MF_EINVAL (id out of range, duplicate id, capacity out of range;
+ * the handle is then unchanged), MF_ESTATE, MF_ETIMEOUT, MF_EDEVICE. */
+MF_API int mf_apply_updates(mf_handle_t *h, const int64_t *edge_ids, const int32_t *new_caps,
+                            int64_t k);
+
+/* As mf_apply_updates, with edge_ids and new_caps in DEVICE memory (k
+ * entries each); validation runs on the device before anything changes. */
+MF_API int mf_apply_updates_device(mf_handle_t *h, const int64_t *d_edge_ids,
+                                   const int32_t *d_new_caps, int64_t k);
+
+/* Change capacities without repairing or solving (host arrays, same rules
+ * as mf_apply_updates).  Leaves the handle unsolved: mf_solve must run before
+ * queries.  This is how the static comparator sees an updated graph. */
+MF_API int mf_set_capacities(mf_handle_t *h, const int64_t *edge_ids, const int32_t *new_caps,
+                             int64_t k);
+
+/* Continue the loop from the current state after MF_ETIMEOUT (or after a
+ * call made with max_iterations == 0).  MF_ESTATE if the flow was never
+ * initialised. */
+MF_API int mf_resume(mf_handle_t *h);
+
+/* Maximum-flow value of the current capacities: e(t) plus the (negative)
+ * excesses of deficient vertices, the sum of e over height-0 vertices of
+ * Alg. 4 (Sec. 4.1.1, final theorem).  MF_ESTATE unless solved. */
+MF_API int mf_flow_value(const mf_handle_t *h, int64_t *out);
+
+/* Minimum cut certificate (Sec. 3.1, Theorem 3 and Note 1): side_out[v] = 1
+ * for the source side S = {v : h(v) >= |V|} left by the final global relabel,
+ * i.e. the vertices that reach neither t nor a deficient vertex in the
+ * residual graph.  This S is the largest minimum source side, the same for
+ * every maximum flow.  cut_cap_out: sum of capacities of edges from S to
+ * V \ S; equal to the flow value.  Either output may be NULL.
+ * side_out: host uint8[n].  MF_ESTATE unless solved. */
+MF_API int mf_min_cut(mf_handle_t *h, uint8_t *side_out, int64_t *cut_cap_out);
+
+/* Change the iteration limit of later calls (< 0 unlimited; 0 runs no
+ * loop round, leaving the state right after initialisation or repair). */
+MF_API int mf_set_max_iterations(mf_handle_t *h, int64_t limit);
+
+/* Counters and timings of the last solving call. */
+MF_API int mf_get_stats(const mf_handle_t *h, mf_stats_t *out);
+
+/* Number of merged arcs A and the per-edge capacity limit: the largest
+ * capacity an edge may take, min(2^30, (2^31-1) / (2k)) for k the largest
+ * number of input edges between one vertex pair, so that an arc's residual
+ * stays inside int32 even after one batch of deltas lands before the clamp. */
+MF_API int mf_num_arcs(const mf_handle_t *h, int32_t *A_out);
+MF_API int mf_cap_limit(const mf_handle_t *h, int32_t *limit_out);
+
+/* Copy the merged layout to host arrays: row_ptr int32[n+1], col int32[A],
+ * twin int32[A] (index of the reverse arc), edge2arc int32[m] (-1 for
+ * self-loops).  Any pointer may be NULL. */
+MF_API int mf_export_graph(mf_handle_t *h, int32_t *row_ptr, int32_t *col, int32_t *twin,
+                           int32_t *edge2arc);
+
+/* Copy the residual state to host arrays: cap int32[A] (current arc
+ * capacities), cf int32[A] (residual capacities), e int64[n] (excesses),
+ * height int32[n] (heights of the last global relabel or sweep), ecap
+ * int32[m] (current per-edge capacities).  Any pointer may be NULL. */
+MF_API int mf_export_state(mf_handle_t *h, int32_t *cap, int32_t *cf, int64_t *e,
+                           int32_t *height, int32_t *ecap);
+
+/* Run the handle's GPU work on `stream` (a hipStream_t; NULL = the
+ * handle's own stream). */
+MF_API int mf_set_stream(mf_handle_t *h, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MF_H */

@@ -1,0 +1,28 @@
+// Host-side construction of the merged arc-pair layout (bi-directional CSR).
+#pragma once
+
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+namespace mf {
+
+struct HostPairs {
+    int32_t n = 0;
+    int64_t m = 0;
+    int32_t A = 0;
+    std::vector<int32_t> row_ptr;   // n+1
+    std::vector<int32_t> col;       // A
+    std::vector<int32_t> twin;      // A
+    std::vector<int32_t> cap;       // A
+    std::vector<int32_t> edge2arc;  // m, -1 for self-loops
+    int32_t max_pair_mult = 1;      // most input edges sharing one arc pair
+};
+
+// Inputs must already be validated (row_ptr monotone 0..m, col in range,
+// cap >= 0).  Returns 0, or -1 with *err set.
+int build_pairs(int32_t n, int64_t m, const int64_t *row_ptr, const int32_t *col, const int32_t *cap,
+                HostPairs *out, std::string *err);
+
+}  // namespace mf

@@ -1,0 +1,805 @@
+// gfx950 kernels for push-relabel max-flow with dynamic capacity updates.
+//
+// Method: Kannappan, Kumar and Nasre, "Efficient Dynamic MaxFlow Computation
+// on GPUs" (arXiv 2511.05895).  Static solve: Sec. 3, Alg. 1-3.  Dynamic
+// repair: Sec. 4.1, Alg. 4-5.  Execution: data-driven worklists (Sec. 5.3) or
+// topology-driven sweeps (Sec. 5.2) over a bi-directional CSR (Sec. 5.1).
+//
+// Design for CDNA4 (not the paper's CUDA design):
+//  * One persistent kernel runs the whole solve loop (global relabel -> active
+//    test -> push/relabel -> invalid-edge removal) with grid-wide barriers
+//    between phases, so no host round trip happens inside a solve.  With one
+//    workgroup the barrier is a plain workgroup barrier.
+//  * The backward BFS expands frontier items of at most kChunk arcs with a
+//    wavefront-wide load-balanced scan (prefix sum over item lengths, each lane
+//    takes one arc), so a hub's arcs spread over many wavefronts and low-degree
+//    frontiers still fill all 64 lanes.  The active worklist is built during the
+//    same BFS (a discovered vertex with positive excess is active), with
+//    ballot/mbcnt compaction and one atomic per wavefront.
+//  * Push/relabel and invalid-edge removal give one lane to a vertex with at
+//    most kLightMaxDeg arcs and a whole wavefront (packed (height, arc) minimum
+//    reduction) to longer lists.  Excess added to t by one wavefront is summed
+//    before a single atomic.
+//  * Memory ordering: residual capacities and excesses that other lanes may be
+//    changing are read with device-scope atomic loads before a push amount is
+//    fixed, so a push never exceeds the latest residual or excess (only the
+//    owner lowers c_f of its arcs and its own excess during a sweep).  Heights
+//    may be stale, which the method tolerates (Sec. 3: invalid edges are
+//    repaired by RemoveInvalidEdges).
+#include "mf_internal.h"
+
+namespace mf {
+
+// ---------------------------------------------------------------------------
+// small device helpers
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
+
+__device__ __forceinline__ int32_t ld_dev(const int32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int64_t ld_dev(const int64_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void add_dev(int32_t *p, int32_t v) {
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void add_dev(int64_t *p, int64_t v) {
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int32_t fetch_add_dev(int32_t *p, int32_t v) {
+    return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int32_t xchg_dev(int32_t *p, int32_t v) {
+    return __hip_atomic_exchange(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ bool cas_dev(int32_t *p, int32_t expected, int32_t desired) {
+    return __hip_atomic_compare_exchange_strong(p, &expected, desired, __ATOMIC_RELAXED,
+                                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// residual capacity field of arc a
+__device__ __forceinline__ int32_t *cf_ptr(int2 *arc, int32_t a) {
+    return reinterpret_cast<int32_t *>(arc) + 2 * (int64_t)a + 1;
+}
+
+__device__ __forceinline__ int wave_incl_scan(int x) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        int y = __shfl_up(x, d, 64);
+        if (lane >= d) x += y;
+    }
+    return x;
+}
+
+__device__ __forceinline__ int64_t wave_sum(int64_t x) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, 64);
+    return x;
+}
+
+__device__ __forceinline__ uint64_t wave_min(uint64_t x) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        uint64_t y = __shfl_xor(x, d, 64);
+        x = y < x ? y : x;
+    }
+    return x;
+}
+
+__device__ __forceinline__ int mask_rank(uint64_t mask) {
+    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                          __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+// Reserve one slot per lane with pred; one atomic per wavefront.  Every lane
+// of the wavefront must call it.  Returns the slot, or -1 without pred.
+__device__ __forceinline__ int wave_append1(int32_t *counter, bool pred) {
+    uint64_t mask = __ballot(pred);
+    if (mask == 0) return -1;
+    int leader = __ffsll((unsigned long long)mask) - 1;
+    int base = 0;
+    if (lane_id() == leader) base = fetch_add_dev(counter, __popcll(mask));
+    base = __shfl(base, leader, 64);
+    return pred ? base + mask_rank(mask) : -1;
+}
+
+// Reserve c slots per lane (c >= 0); one atomic per wavefront.  Every lane must
+// call it.  Returns the first slot of this lane's range.
+__device__ __forceinline__ int wave_appendn(int32_t *counter, int c) {
+    int incl = wave_incl_scan(c);
+    int total = __shfl(incl, 63, 64);
+    if (total == 0) return 0;
+    int base = 0;
+    if (lane_id() == 63) base = fetch_add_dev(counter, total);
+    base = __shfl(base, 63, 64);
+    return base + incl - c;
+}
+
+__device__ __forceinline__ int n_items(int deg) { return (deg + kChunk - 1) / kChunk; }
+
+// Grid-wide barrier with a bounded wait.  Returns false when the wait ran out
+// (wall clock, `limit` ticks) or another workgroup aborted; the caller must then
+// leave the kernel, so every workgroup ends even if co-residency ever failed.
+__device__ bool grid_barrier(Ctrl *c, int64_t limit) {
+    if (gridDim.x == 1) {
+        __syncthreads();
+        return true;
+    }
+    __shared__ int s_ok;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int ok = 1;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        uint32_t gen = __hip_atomic_load(&c->bar_gen.v, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        uint32_t arrived =
+            __hip_atomic_fetch_add(&c->bar_count.v, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (arrived == gridDim.x - 1) {
+            __hip_atomic_store(&c->bar_count.v, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&c->bar_gen.v, gen + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            const uint64_t tw = wall_clock64();
+            uint32_t spins = 0;
+            while (__hip_atomic_load(&c->bar_gen.v, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+                __builtin_amdgcn_s_sleep(1);
+                if ((++spins & 255u) == 0) {
+                    if (__hip_atomic_load(&c->abort.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                        ok = 0;
+                        break;
+                    }
+                    if ((int64_t)(wall_clock64() - tw) > limit) {
+                        __hip_atomic_store(&c->abort.v, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        ok = 0;
+                        break;
+                    }
+                }
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        s_ok = ok;
+    }
+    __syncthreads();
+    return s_ok != 0;
+}
+
+// Per-thread event counters, summed into Ctrl::stat at kernel end.
+struct Tally {
+    int64_t bfs_v = 0, bfs_a = 0, pr_cyc = 0, pr_a = 0, push = 0, relabel = 0, rie_a = 0, rie_sat = 0;
+};
+
+template <int BLOCK>
+__device__ void flush_tally(Ctrl *c, const Tally &t) {
+    __shared__ int64_t s_acc[8];
+    if (threadIdx.x < 8) s_acc[threadIdx.x] = 0;
+    __syncthreads();
+    int64_t v[8] = {t.bfs_v, t.bfs_a, t.pr_cyc, t.pr_a, t.push, t.relabel, t.rie_a, t.rie_sat};
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        int64_t w = wave_sum(v[i]);
+        if (lane_id() == 0 && w) atomicAdd((unsigned long long *)&s_acc[i], (unsigned long long)w);
+    }
+    __syncthreads();
+    const int slot[8] = {kStBfsVertices, kStBfsArcs, kStPrCycles, kStPrArcs,
+                         kStPushes,      kStRelabels, kStRieArcs, kStRieSat};
+    if (threadIdx.x < 8 && s_acc[threadIdx.x]) add_dev(&c->stat[slot[threadIdx.x]], s_acc[threadIdx.x]);
+}
+
+// ---------------------------------------------------------------------------
+// Global relabel (Alg. 4 height reset + BFS_Backward)
+// ---------------------------------------------------------------------------
+
+// Height reset: t and every deficient vertex other than s are roots (height
+// 0); all others get |V|.  Roots become the level-0 frontier.
+__device__ void bfs_roots(const DevGraph &g, Tally &tl) {
+    const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t nr = ((int64_t)g.n + 63) & ~63ll;
+    for (int64_t i = gtid; i < nr; i += stride) {
+        const int v = (int)i;
+        bool root = false;
+        int deg = 0, beg = 0;
+        if (i < g.n) {
+            root = (v == g.t) || (v != g.s && g.e[v] < 0);
+            g.h[v] = root ? 0 : g.n;
+            if (root) {
+                beg = g.row_ptr[v];
+                deg = g.row_ptr[v + 1] - beg;
+            }
+        }
+        const int c = root ? n_items(deg) : 0;
+        const int base = wave_appendn(&g.ctrl->qcount[0], c);
+        for (int j = 0; j < c; ++j) g.q[0][base + j] = make_int2(v, beg + j * kChunk);
+        tl.bfs_v += root;
+    }
+}
+
+// One BFS level, top-down: for every arc (w -> v) of a frontier item, v joins
+// level L+1 when it is unvisited (height |V|), is not s, and has residual
+// capacity toward w (the twin arc v -> w).  Newly reached vertices become
+// frontier items of the next level; those with positive excess go to the
+// active worklist (A of Alg. 1: e > 0 and h < |V|, s and t excluded).
+__device__ void bfs_level(const DevGraph &g, int L, Tally &tl) {
+    const int2 *__restrict__ qin = g.q[L & 1];
+    int2 *qout = g.q[(L + 1) & 1];
+    const int cnt = ld_dev(&g.ctrl->qcount[L % 3]);
+    int32_t *qout_count = &g.ctrl->qcount[(L + 1) % 3];
+    const int lane = lane_id();
+    const int64_t wpb = blockDim.x >> 6;
+    const int64_t gwave = (int64_t)blockIdx.x * wpb + (threadIdx.x >> 6);
+    const int64_t nwaves = (int64_t)gridDim.x * wpb;
+    const int n = g.n;
+    for (int64_t base = gwave * 64; base < cnt; base += nwaves * 64) {
+        const int64_t idx = base + lane;
+        int beg = 0, len = 0;
+        if (idx < cnt) {
+            const int2 it = qin[idx];
+            beg = it.y;
+            const int end = min(beg + kChunk, g.row_ptr[it.x + 1]);
+            len = end - beg;
+        }
+        const int incl = wave_incl_scan(len);
+        const int excl = incl - len;
+        const int total = __shfl(incl, 63, 64);
+        for (int off = 0; off < total; off += 64) {
+            const int j = off + lane;
+            // largest lane o with excl[o] <= j (that lane has len > 0)
+            int o = 0;
+#pragma unroll
+            for (int step = 32; step >= 1; step >>= 1) {
+                const int cand = o + step;
+                const int ex = __shfl(excl, cand, 64);
+                if (ex <= j) o = cand;
+            }
+            const int obeg = __shfl(beg, o, 64);
+            const int oexcl = __shfl(excl, o, 64);
+            bool disc = false;
+            int v = -1;
+            if (j < total) {
+                const int a = obeg + (j - oexcl);
+                v = g.arc[a].x;
+                tl.bfs_a++;
+                if (v != g.s && g.h[v] == n) {
+                    const int tw = g.twin[a];
+                    if (g.arc[tw].y > 0) disc = cas_dev(&g.h[v], n, L + 1);
+                }
+            }
+            int vbeg = 0, vdeg = 0;
+            bool active = false;
+            if (disc) {
+                vbeg = g.row_ptr[v];
+                vdeg = g.row_ptr[v + 1] - vbeg;
+                active = (v != g.t) && g.e[v] > 0;
+                tl.bfs_v++;
+            }
+            const int c = disc ? n_items(vdeg) : 0;
+            const int qb = wave_appendn(qout_count, c);
+            for (int k = 0; k < c; ++k) qout[qb + k] = make_int2(v, vbeg + k * kChunk);
+            const bool light = active && vdeg <= kLightMaxDeg;
+            const bool heavy = active && vdeg > kLightMaxDeg;
+            const int sl = wave_append1(&g.ctrl->nlight, light);
+            if (light) g.wl_light[sl] = v;
+            const int sh = wave_append1(&g.ctrl->nheavy, heavy);
+            if (heavy) g.wl_heavy[sh] = v;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// PushRelabel (Alg. 2)
+// ---------------------------------------------------------------------------
+
+// One lane per vertex.  Every lane of the wavefront runs all kc cycles so the
+// wavefront stays converged for the aggregated excess update of t.
+__device__ void push_relabel_lanes(const DevGraph &g, const int32_t *list, int64_t count,
+                                   bool topology, int kc, Tally &tl) {
+    const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t cr = (count + 63) & ~63ll;
+    const int n = g.n;
+    const int lane = lane_id();
+    for (int64_t i = gtid; i < cr; i += stride) {
+        int u = -1, beg = 0, end = 0, hu = n;
+        if (i < count) {
+            u = topology ? (int)i : list[i];
+            beg = g.row_ptr[u];
+            end = g.row_ptr[u + 1];
+            if (topology && (end - beg > kLightMaxDeg || u == g.s || u == g.t)) u = -1;
+            if (u >= 0) hu = g.h[u];
+        }
+        for (int cyc = 0; cyc < kc; ++cyc) {
+            bool act = u >= 0 && hu < n;
+            int64_t eu = 0;
+            if (act) {
+                eu = ld_dev(&g.e[u]);
+                act = eu > 0;
+            }
+            int tgt = -1;
+            int64_t d = 0;
+            if (act) {
+                tl.pr_cyc++;
+                uint64_t best = ~0ull;
+                for (int a = beg; a < end; ++a) {
+                    const int2 r = g.arc[a];
+                    if (r.y > 0) {
+                        const uint64_t key = ((uint64_t)(uint32_t)g.h[r.x] << 32) | (uint32_t)a;
+                        best = key < best ? key : best;
+                    }
+                }
+                tl.pr_a += end - beg;
+                if (best != ~0ull) {
+                    const int hh = (int)(best >> 32);
+                    const int ah = (int)(uint32_t)best;
+                    if (hu > hh) {
+                        int32_t *cfa = cf_ptr(g.arc, ah);
+                        const int32_t cfl = ld_dev(cfa);
+                        d = eu < (int64_t)cfl ? eu : (int64_t)cfl;
+                        if (d > 0) {
+                            add_dev(cfa, -(int32_t)d);
+                            add_dev(cf_ptr(g.arc, g.twin[ah]), (int32_t)d);
+                            add_dev(&g.e[u], -d);
+                            tgt = g.arc[ah].x;
+                            tl.push++;
+                        }
+                    } else {
+                        hu = hh + 1;
+                        g.h[u] = hu;
+                        tl.relabel++;
+                    }
+                }
+            }
+            const bool to_t = tgt == g.t;
+            const uint64_t mt = __ballot(to_t);
+            if (mt) {
+                const int64_t sum = wave_sum(to_t ? d : 0);
+                if (lane == __ffsll((unsigned long long)mt) - 1) add_dev(&g.e[g.t], sum);
+            }
+            if (tgt >= 0 && !to_t) add_dev(&g.e[tgt], d);
+        }
+    }
+}
+
+// One wavefront per vertex: lanes scan the arc list, a packed (height, arc)
+// minimum picks the lowest residual neighbour (first in arc order on ties),
+// lane 0 pushes or relabels.
+__device__ void push_relabel_waves(const DevGraph &g, const int32_t *list, int64_t count, int kc,
+                                   Tally &tl) {
+    const int lane = lane_id();
+    const int64_t wpb = blockDim.x >> 6;
+    const int64_t gwave = (int64_t)blockIdx.x * wpb + (threadIdx.x >> 6);
+    const int64_t nwaves = (int64_t)gridDim.x * wpb;
+    const int n = g.n;
+    for (int64_t i = gwave; i < count; i += nwaves) {
+        const int u = list[i];
+        const int beg = g.row_ptr[u], end = g.row_ptr[u + 1];
+        int hu = g.h[u];
+        for (int cyc = 0; cyc < kc; ++cyc) {
+            int64_t eu = 0;
+            if (lane == 0) eu = ld_dev(&g.e[u]);
+            eu = __shfl(eu, 0, 64);
+            if (eu <= 0 || hu >= n) break;
+            if (lane == 0) tl.pr_cyc++;
+            uint64_t best = ~0ull;
+            for (int a = beg + lane; a < end; a += 64) {
+                const int2 r = g.arc[a];
+                if (r.y > 0) {
+                    const uint64_t key = ((uint64_t)(uint32_t)g.h[r.x] << 32) | (uint32_t)a;
+                    best = key < best ? key : best;
+                }
+            }
+            if (lane == 0) tl.pr_a += end - beg;
+            best = wave_min(best);
+            if (best == ~0ull) break;
+            const int hh = (int)(best >> 32);
+            const int ah = (int)(uint32_t)best;
+            if (hu > hh) {
+                if (lane == 0) {
+                    int32_t *cfa = cf_ptr(g.arc, ah);
+                    const int32_t cfl = ld_dev(cfa);
+                    const int64_t d = eu < (int64_t)cfl ? eu : (int64_t)cfl;
+                    if (d > 0) {
+                        add_dev(cfa, -(int32_t)d);
+                        add_dev(cf_ptr(g.arc, g.twin[ah]), (int32_t)d);
+                        add_dev(&g.e[u], -d);
+                        add_dev(&g.e[g.arc[ah].x], d);
+                        tl.push++;
+                    }
+                }
+            } else {
+                hu = hh + 1;
+                if (lane == 0) {
+                    g.h[u] = hu;
+                    tl.relabel++;
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// RemoveInvalidEdges (Alg. 3): saturate every residual arc (u, v) with
+// h(u) > h(v) + 1.  Only u lowers c_f of its own arcs, so an exchange with 0
+// reads and clears the residual in one step.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ void rie_arc(const DevGraph &g, int u, int hu, int a, Tally &tl) {
+    const int2 r = g.arc[a];
+    if (r.y > 0 && hu > g.h[r.x] + 1) {
+        const int32_t c = xchg_dev(cf_ptr(g.arc, a), 0);
+        if (c > 0) {
+            add_dev(cf_ptr(g.arc, g.twin[a]), c);
+            add_dev(&g.e[u], -(int64_t)c);
+            add_dev(&g.e[r.x], (int64_t)c);
+            tl.rie_sat++;
+        }
+    }
+}
+
+__device__ void remove_invalid_lanes(const DevGraph &g, const int32_t *list, int64_t count,
+                                     bool topology, Tally &tl) {
+    const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = gtid; i < count; i += stride) {
+        const int u = topology ? (int)i : list[i];
+        const int beg = g.row_ptr[u], end = g.row_ptr[u + 1];
+        if (topology && end - beg > kLightMaxDeg) continue;
+        const int hu = g.h[u];
+        for (int a = beg; a < end; ++a) rie_arc(g, u, hu, a, tl);
+        tl.rie_a += end - beg;
+    }
+}
+
+__device__ void remove_invalid_waves(const DevGraph &g, const int32_t *list, int64_t count, Tally &tl) {
+    const int lane = lane_id();
+    const int64_t wpb = blockDim.x >> 6;
+    const int64_t gwave = (int64_t)blockIdx.x * wpb + (threadIdx.x >> 6);
+    const int64_t nwaves = (int64_t)gridDim.x * wpb;
+    for (int64_t i = gwave; i < count; i += nwaves) {
+        const int u = list[i];
+        const int beg = g.row_ptr[u], end = g.row_ptr[u + 1];
+        const int hu = g.h[u];
+        for (int a = beg + lane; a < end; a += 64) rie_arc(g, u, hu, a, tl);
+        if (lane == 0) tl.rie_a += end - beg;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// The persistent solve loop (Alg. 1 / Alg. 4 while-loop)
+// ---------------------------------------------------------------------------
+
+template <int BLOCK>
+__global__ void __launch_bounds__(BLOCK) k_loop(DevGraph g, LoopParams p) {
+    Ctrl *c = g.ctrl;
+    if (ld_dev(&c->err)) return;  // update batch rejected: leave the state alone
+    Tally tl;
+    const bool leader = blockIdx.x == 0 && threadIdx.x == 0;
+    const bool topology = p.mode == 1;
+    int64_t iter = 0;
+    const uint64_t t0 = wall_clock64();
+    for (;;) {
+        // time budget: the leader raised `stop` before the last barrier, so
+        // every workgroup sees the same value here
+        if (ld_dev(&c->stop)) {
+            if (leader) c->status = kDeadline;
+            break;
+        }
+        // --- global relabel ---
+        if (leader) {
+            c->nlight = 0;
+            c->nheavy = 0;
+            add_dev(&c->stat[kStGlobalRelabels], 1);
+        }
+        bfs_roots(g, tl);
+        if (!grid_barrier(c, p.barrier_ticks)) return;
+        int L = 0;
+        for (;;) {
+            const int cnt = ld_dev(&c->qcount[L % 3]);
+            if (cnt == 0) break;
+            if (leader) c->qcount[(L + 2) % 3] = 0;
+            bfs_level(g, L, tl);
+            if (!grid_barrier(c, p.barrier_ticks)) return;
+            ++L;
+        }
+        if (leader) add_dev(&c->stat[kStLevels], (int64_t)L);
+        // --- termination test right after a fresh global relabel ---
+        const int nl = ld_dev(&c->nlight);
+        const int nh = ld_dev(&c->nheavy);
+        if (nl + nh == 0) {
+            if (leader) c->status = kSolved;
+            break;
+        }
+        if (p.max_iter >= 0 && iter >= p.max_iter) {
+            if (leader) c->status = kIterLimit;
+            break;
+        }
+        // --- PushRelabel ---
+        if (topology) {
+            push_relabel_lanes(g, nullptr, g.n, true, p.kc, tl);
+            push_relabel_waves(g, g.heavy_all, g.n_heavy_all, p.kc, tl);
+        } else {
+            push_relabel_lanes(g, g.wl_light, nl, false, p.kc, tl);
+            push_relabel_waves(g, g.wl_heavy, nh, p.kc, tl);
+        }
+        if (!grid_barrier(c, p.barrier_ticks)) return;
+        // --- RemoveInvalidEdges ---
+        if (topology) {
+            remove_invalid_lanes(g, nullptr, g.n, true, tl);
+            remove_invalid_waves(g, g.heavy_all, g.n_heavy_all, tl);
+        } else {
+            remove_invalid_lanes(g, g.wl_light, nl, false, tl);
+            remove_invalid_waves(g, g.wl_heavy, nh, tl);
+        }
+        if (leader) {
+            c->qcount[0] = 0;
+            c->qcount[1] = 0;
+            c->qcount[2] = 0;
+            add_dev(&c->stat[kStIterations], 1);
+            if ((int64_t)(wall_clock64() - t0) > p.deadline_ticks) c->stop = 1;
+        }
+        if (!grid_barrier(c, p.barrier_ticks)) return;
+        ++iter;
+    }
+    // --- value: e(t) plus the deficits of vertices other than s and t ---
+    // (every workgroup reaches this point after the same, uniform decision)
+    {
+        __shared__ int64_t s_def;
+        if (threadIdx.x == 0) s_def = 0;
+        __syncthreads();
+        int64_t part = 0;
+        for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < g.n;
+             v += (int64_t)gridDim.x * blockDim.x) {
+            const int64_t ev = g.e[v];
+            if (ev < 0 && v != g.s && v != g.t) part += ev;
+        }
+        part = wave_sum(part);
+        if (lane_id() == 0 && part) atomicAdd((unsigned long long *)&s_def, (unsigned long long)part);
+        __syncthreads();
+        if (threadIdx.x == 0 && s_def) add_dev(&c->deficit, s_def);
+        if (leader) c->e_t = g.e[g.t];
+    }
+    flush_tally<BLOCK>(c, tl);
+}
+
+// ---------------------------------------------------------------------------
+// Initialisation, source saturation and update repair
+// ---------------------------------------------------------------------------
+
+__global__ void k_reset_ctrl(Ctrl *c) {
+    int *w = reinterpret_cast<int *>(c);
+    const int words = (int)(sizeof(Ctrl) / sizeof(int));
+    for (int i = threadIdx.x; i < words; i += blockDim.x) w[i] = 0;
+}
+
+// Alg. 1 first loops: e = 0, h = 0, c_f = c.
+__global__ void k_init_state(DevGraph g) {
+    const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t a = gtid; a < g.A; a += stride) g.arc[a].y = g.cap[a];
+    for (int64_t v = gtid; v < g.n; v += stride) {
+        g.e[v] = 0;
+        g.h[v] = 0;
+    }
+}
+
+// Saturate every residual arc out of s: c_f(s,u) -> 0, the twin gains it,
+// e(u) += d, e(s) -= d (Alg. 1 third loop; Alg. 4 lines 3-8, where the
+// remaining residual is pushed rather than e(u) overwritten).
+__global__ void k_saturate_source(DevGraph g) {
+    if (ld_dev(&g.ctrl->err)) return;
+    __shared__ int64_t s_sum, s_cnt;
+    if (threadIdx.x == 0) {
+        s_sum = 0;
+        s_cnt = 0;
+    }
+    __syncthreads();
+    const int beg = g.row_ptr[g.s], end = g.row_ptr[g.s + 1];
+    int64_t sum = 0, cnt = 0;
+    for (int64_t a = beg + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; a < end;
+         a += (int64_t)gridDim.x * blockDim.x) {
+        const int2 r = g.arc[a];
+        if (r.y > 0) {
+            g.arc[a].y = 0;
+            add_dev(cf_ptr(g.arc, g.twin[a]), r.y);
+            add_dev(&g.e[r.x], (int64_t)r.y);
+            sum += r.y;
+            cnt++;
+        }
+    }
+    sum = wave_sum(sum);
+    cnt = wave_sum(cnt);
+    if (lane_id() == 0 && sum) {
+        atomicAdd((unsigned long long *)&s_sum, (unsigned long long)sum);
+        atomicAdd((unsigned long long *)&s_cnt, (unsigned long long)cnt);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && s_sum) {
+        add_dev(&g.e[g.s], -s_sum);
+        add_dev(&g.ctrl->stat[kStSourcePushes], s_cnt);
+    }
+}
+
+// Batch validation: ids in [0, m), capacities in [0, cap_limit], ids distinct
+// (a batch is a set).  Sets Ctrl::err; later kernels of the call then skip.
+__global__ void k_validate_updates(DevGraph g, const int64_t *ids, const int32_t *caps, int64_t k,
+                                   int32_t epoch, int32_t cap_limit) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < k;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t id = ids[i];
+        const int32_t cv = caps[i];
+        if (id < 0 || id >= g.m) {
+            atomicOr(&g.ctrl->err, 1);
+            continue;
+        }
+        if (cv < 0 || cv > cap_limit) atomicOr(&g.ctrl->err, 2);
+        if (atomicExch(&g.stamp[id], epoch) == epoch) atomicOr(&g.ctrl->err, 4);
+    }
+}
+
+// Alg. 5 first loop: c_f(u,v) += c' - c; the stored capacities follow.
+__global__ void k_apply_delta(DevGraph g, const int64_t *ids, const int32_t *caps, int64_t k) {
+    if (ld_dev(&g.ctrl->err)) return;
+    int64_t cnt = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < k;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t id = ids[i];
+        const int32_t cv = caps[i];
+        const int32_t d = cv - g.ecap[id];
+        g.ecap[id] = cv;
+        const int32_t a = g.edge2arc[id];
+        if (a >= 0 && d != 0) {
+            add_dev(&g.cap[a], d);
+            add_dev(cf_ptr(g.arc, a), d);
+        }
+        cnt++;
+    }
+    cnt = wave_sum(cnt);
+    if (lane_id() == 0 && cnt) add_dev(&g.ctrl->stat[kStUpdates], cnt);
+}
+
+// Alg. 5 second loop restricted to the updated arc pairs (only they can have
+// gone negative), with the excess change booked at once: the flow clamped by
+// o = -c_f(a) returns o units to the tail (e += o) and takes them from the
+// head (e -= o).  At most one arc of a pair can be negative (their residuals
+// sum to the pair's capacity); a compare-and-swap makes each clamp happen
+// once even when several updates share a pair.
+__global__ void k_clamp(DevGraph g, const int64_t *ids, int64_t k) {
+    if (ld_dev(&g.ctrl->err)) return;
+    int64_t cnt = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < k;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t a0 = g.edge2arc[ids[i]];
+        if (a0 < 0) continue;
+        const int32_t a1 = g.twin[a0];
+        for (int side = 0; side < 2; ++side) {
+            const int32_t x = side ? a1 : a0;
+            const int32_t y = side ? a0 : a1;
+            int32_t *cfx = cf_ptr(g.arc, x);
+            const int32_t cv = ld_dev(cfx);
+            if (cv < 0 && cas_dev(cfx, cv, 0)) {
+                const int32_t o = -cv;
+                add_dev(cf_ptr(g.arc, y), -o);
+                add_dev(&g.e[g.arc[y].x], (int64_t)o);  // tail of x
+                add_dev(&g.e[g.arc[x].x], -(int64_t)o); // head of x
+                cnt++;
+            }
+        }
+    }
+    cnt = wave_sum(cnt);
+    if (lane_id() == 0 && cnt) add_dev(&g.ctrl->stat[kStClamps], cnt);
+}
+
+// Certificate: side[v] = 1 when h(v) >= |V|; cut = sum of cap over arcs from
+// the source side to the sink side (the tail of arc a is the head of twin(a)).
+__global__ void k_min_cut(DevGraph g, uint8_t *side) {
+    __shared__ int64_t s_cut;
+    if (threadIdx.x == 0) s_cut = 0;
+    __syncthreads();
+    const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    if (side)
+        for (int64_t v = gtid; v < g.n; v += stride) side[v] = g.h[v] >= g.n ? 1 : 0;
+    int64_t part = 0;
+    for (int64_t a = gtid; a < g.A; a += stride) {
+        const int head = g.arc[a].x;
+        const int tail = g.arc[g.twin[a]].x;
+        if (g.h[tail] >= g.n && g.h[head] < g.n) part += g.cap[a];
+    }
+    part = wave_sum(part);
+    if (lane_id() == 0 && part) atomicAdd((unsigned long long *)&s_cut, (unsigned long long)part);
+    __syncthreads();
+    if (threadIdx.x == 0 && s_cut) add_dev(&g.ctrl->cut, s_cut);
+}
+
+__global__ void k_fill_i32(int32_t *p, int64_t count, int32_t value) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = value;
+}
+
+// ---------------------------------------------------------------------------
+// launch wrappers
+// ---------------------------------------------------------------------------
+
+static int grid_for(int64_t work, int block, int cap = 8192) {
+    int64_t b = (work + block - 1) / block;
+    if (b < 1) b = 1;
+    if (b > cap) b = cap;
+    return (int)b;
+}
+
+hipError_t launch_reset_ctrl(const DevGraph &g, hipStream_t st) {
+    hipLaunchKernelGGL(k_reset_ctrl, dim3(1), dim3(256), 0, st, g.ctrl);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_state(const DevGraph &g, hipStream_t st) {
+    const int64_t work = g.A > g.n ? g.A : g.n;
+    hipLaunchKernelGGL(k_init_state, dim3(grid_for(work, 256)), dim3(256), 0, st, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_saturate_source(const DevGraph &g, hipStream_t st) {
+    // the degree of s is only known on the host side of the handle; a fixed
+    // grid with grid-stride loops covers any degree
+    hipLaunchKernelGGL(k_saturate_source, dim3(256), dim3(256), 0, st, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_validate_updates(const DevGraph &g, const int64_t *ids, const int32_t *caps,
+                                   int64_t k, int32_t epoch, int32_t cap_limit, hipStream_t st) {
+    if (k <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_validate_updates, dim3(grid_for(k, 256)), dim3(256), 0, st, g, ids, caps, k,
+                       epoch, cap_limit);
+    return hipGetLastError();
+}
+
+hipError_t launch_apply_delta(const DevGraph &g, const int64_t *ids, const int32_t *caps, int64_t k,
+                              hipStream_t st) {
+    if (k <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_apply_delta, dim3(grid_for(k, 256)), dim3(256), 0, st, g, ids, caps, k);
+    return hipGetLastError();
+}
+
+hipError_t launch_clamp(const DevGraph &g, const int64_t *ids, int64_t k, hipStream_t st) {
+    if (k <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_clamp, dim3(grid_for(k, 256)), dim3(256), 0, st, g, ids, k);
+    return hipGetLastError();
+}
+
+hipError_t loop_max_coresident(int device, int *blocks) {
+    int per_cu = 0, cus = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &per_cu, reinterpret_cast<const void *>(k_loop<kBlock>), kBlock, 0);
+    if (e != hipSuccess) return e;
+    e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
+    if (e != hipSuccess) return e;
+    *blocks = per_cu * cus;
+    return hipSuccess;
+}
+
+hipError_t launch_loop(const DevGraph &g, const LoopParams &p, int grid, hipStream_t st) {
+    if (grid <= 1) {
+        hipLaunchKernelGGL(k_loop<kBlockSingle>, dim3(1), dim3(kBlockSingle), 0, st, g, p);
+        return hipGetLastError();
+    }
+    DevGraph ga = g;
+    LoopParams pa = p;
+    void *args[] = {&ga, &pa};
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_loop<kBlock>), dim3(grid),
+                                      dim3(kBlock), args, 0, st);
+}
+
+hipError_t launch_min_cut(const DevGraph &g, uint8_t *d_side, hipStream_t st) {
+    const int64_t work = g.A > g.n ? g.A : g.n;
+    hipLaunchKernelGGL(k_min_cut, dim3(grid_for(work, 256, 2048)), dim3(256), 0, st, g, d_side);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(int32_t *p, int64_t count, int32_t value, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(count, 256)), dim3(256), 0, st, p, count, value);
+    return hipGetLastError();
+}
+
+}  // namespace mf

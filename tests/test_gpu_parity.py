@@ -1,0 +1,306 @@
+"""GPU parity: the HIP path (through the C-ABI) against the CPU oracle.
+
+Values must match bit for bit, the canonical minimum cut element by element,
+the merged layout and the deterministic steps (initialisation, update repair,
+BFS heights) bit for bit; racy sweeps are checked through the validator."""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from tests.gpu_util import check_layout, check_solved
+from tests.graphs import from_edges, tiny_random
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mf():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2511_05895_amd import mf as m
+    return m
+
+
+# ---------------- tiny graphs: every configuration ----------------
+
+@pytest.mark.parametrize("seed", range(120))
+def test_tiny_static_and_dynamic(mf, seed):
+    g = tiny_random(seed, n_hi=14, m_hi=50)
+    with mf.MaxFlow(g) as F:
+        F.solve()
+        check_solved(F, g, g.cap)
+        rng = np.random.default_rng(seed)
+        cap = g.cap.copy()
+        for _ in range(3):
+            if g.m == 0:
+                break
+            k = int(rng.integers(1, g.m + 1))
+            ids = rng.choice(g.m, k, replace=False).astype(np.int64)
+            new = rng.integers(0, 12, k).astype(np.int32)
+            cap[ids] = new
+            F.update(ids, new)
+            check_solved(F, g, cap)
+            if g.n <= 16:
+                assert F.value() == O.brute_force_min_cut(g, cap)[0]
+
+
+@pytest.mark.parametrize("grid", [1, 2, 8, 64])
+@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("kc", [0, 1, 3, 40])
+def test_c1_launch_shapes(mf, grid, mode, kc):
+    g = W.c1_random_1k()
+    with mf.MaxFlow(g, grid_blocks=grid, mode=mode, kernel_cycles=kc) as F:
+        F.solve()
+        check_solved(F, g, g.cap)
+        cap = g.cap.copy()
+        for ids, new in W.batch_chain(g, 0.0125, 3, 100, seed=W.SEED_BASE + 7):
+            cap[ids] = new
+            F.update(ids, new)
+            check_solved(F, g, cap)
+
+
+def test_c1_chain_against_recompute(mf):
+    """Config: 1,000 vertices, 8,000 edges, caps U[1,100]; static then a chain
+    of 100-update mixed batches, each checked against a from-scratch oracle."""
+    g = W.c1_random_1k()
+    with mf.MaxFlow(g) as F:
+        F.solve()
+        check_solved(F, g, g.cap)
+        cap = g.cap.copy()
+        for ids, new in W.batch_chain(g, 0.0125, 20, 100, seed=W.SEED_BASE):
+            cap[ids] = new
+            F.update(ids, new)
+            check_solved(F, g, cap)
+
+
+# ---------------- deterministic steps, bit-exact against the sequential paper route ----------------
+
+def test_init_state_matches_paper_init(mf):
+    g = W.random_graph(500, 4000, 0, 60, seed=21, s=3, t=400)
+    p = O.PaperSeq(g)
+    p.init()
+    with mf.MaxFlow(g, max_iterations=0) as F:
+        with pytest.raises(mf.MfError) as ei:
+            F.solve()
+        assert ei.value.code == mf.MF_ETIMEOUT
+        cap, cf, e, h, ecap = F.export_state()
+        assert np.array_equal(cf, p.cf) and np.array_equal(e, p.e)
+        # the global relabel of the first round ran; its heights are exact
+        assert np.array_equal(h, O.bfs_heights(p.pg, p.cf, p.e))
+        F.set_max_iterations(-1)
+        F.resume()
+        check_solved(F, g, g.cap)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_update_repair_matches_paper_updates(mf, seed):
+    g = W.random_graph(400, 3200, 1, 50, seed=100 + seed, s=0, t=399)
+    rng = np.random.default_rng(seed)
+    with mf.MaxFlow(g) as F:
+        F.solve()
+        cap = g.cap.copy()
+        for j in range(3):
+            cap0, cf0, e0, _, ecap0 = F.export_state()
+            ids, new = W.mixed_batch(cap, int(rng.integers(1, 400)), 50, rng)
+            p = O.PaperSeq(g, cap=cap)
+            p.cf[:] = cf0
+            p.e[:] = e0
+            assert np.array_equal(p.pg.cap, cap0)
+            p.apply_updates(ids, new)
+            cap[ids] = new
+            F.set_max_iterations(0)
+            try:
+                F.update(ids, new)
+            except mf.MfError as ex:
+                assert ex.code == mf.MF_ETIMEOUT
+            capg, cfg, eg, hg, ecapg = F.export_state()
+            assert np.array_equal(capg, p.pg.cap)
+            assert np.array_equal(cfg, p.cf)
+            assert np.array_equal(eg, p.e)
+            assert np.array_equal(ecapg, cap)
+            F.set_max_iterations(-1)
+            F.resume()
+            check_solved(F, g, cap)
+
+
+def test_clamp_with_parallel_and_antiparallel_edges(mf):
+    """Several updates land on one arc pair (duplicates and the reverse
+    direction) in the same batch; the clamp must act once on the summed delta."""
+    edges = [(0, 1, 50), (1, 2, 30), (1, 2, 20), (2, 1, 5), (2, 3, 60), (1, 3, 10), (3, 2, 4)]
+    g = from_edges(4, edges, 0, 3)
+    with mf.MaxFlow(g) as F:
+        F.solve()
+        check_solved(F, g, g.cap)
+        cap = g.cap.copy()
+        tails = g.tails()
+        sel = np.nonzero(((tails == 1) & (g.col == 2)) | ((tails == 2) & (g.col == 1)))[0]
+        ids = sel.astype(np.int64)
+        new = np.zeros(ids.shape[0], dtype=np.int32)
+        cap[ids] = new
+        F.update(ids, new)
+        check_solved(F, g, cap)
+
+
+# ---------------- paper-scale workloads ----------------
+
+def test_c2_grid_static_and_batches(mf):
+    """Config: 512x512 segmentation grid, 1% mixed batches."""
+    g = W.c2_grid_512()
+    with mf.MaxFlow(g) as F:
+        F.solve()
+        check_solved(F, g, g.cap, oracle="fifo")
+        cap = g.cap.copy()
+        for ids, new in W.batch_chain(g, 0.01, 2, 100, seed=W.SEED_BASE + 1):
+            cap[ids] = new
+            F.update(ids, new)
+            check_solved(F, g, cap, oracle="fifo")
+
+
+def test_c3_rmat_static_and_batch(mf):
+    """Config: R-MAT scale 20, 0.1% and 1% mixed batches (full parity at the
+    full size: value, cut, validator, heights)."""
+    g = W.c3_rmat20()
+    with mf.MaxFlow(g) as F:
+        F.solve()
+        check_solved(F, g, g.cap, oracle="fifo")
+        cap = g.cap.copy()
+        for frac in (0.001, 0.01):
+            ids, new = W.mixed_batch(cap, W.batch_size(g.m, frac), 1000,
+                                     W.rng_for(W.SEED_BASE + 2, 9, int(frac * 1e4)))
+            cap[ids] = new
+            F.update(ids, new)
+            check_solved(F, g, cap, oracle="fifo")
+
+
+# ---------------- static comparator path ----------------
+
+def test_set_capacities_then_static_equals_dynamic(mf):
+    g = W.random_graph(2000, 16000, 1, 100, seed=5, s=0, t=1999)
+    ids, new = W.mixed_batch(g.cap, 500, 100, np.random.default_rng(1))
+    cap = W.apply_batch(g.cap, ids, new)
+    with mf.MaxFlow(g) as D, mf.MaxFlow(g) as S:
+        D.solve()
+        vd = D.update(ids, new)
+        S.set_capacities(ids, new)
+        with pytest.raises(mf.MfError) as ei:
+            S.value()
+        assert ei.value.code == mf.MF_ESTATE
+        vs = S.solve()
+        assert vd == vs == O.dinic(g, cap)[0]
+        assert np.array_equal(D.min_cut()[0], S.min_cut()[0])
+
+
+def test_device_batch_from_torch(mf):
+    import torch
+    g = W.c1_random_1k()
+    ids, new = next(W.batch_chain(g, 0.0125, 1, 100, seed=3))
+    cap = W.apply_batch(g.cap, ids, new)
+    with mf.MaxFlow(g) as F:
+        F.solve()
+        di = torch.from_numpy(ids).to("cuda")
+        dc = torch.from_numpy(new).to("cuda")
+        torch.cuda.synchronize()
+        F.update_device(di, dc)
+        check_solved(F, g, cap)
+
+
+# ---------------- error paths ----------------
+
+def test_errors_leave_the_handle_unchanged(mf):
+    g = W.c1_random_1k()
+    with mf.MaxFlow(g) as F:
+        with pytest.raises(mf.MfError) as ei:
+            F.update(np.array([0], np.int64), np.array([1], np.int32))
+        assert ei.value.code == mf.MF_ESTATE
+        v = F.solve()
+        before = F.export_state()
+        bad = [
+            (np.array([3, 3], np.int64), np.array([1, 2], np.int32)),       # duplicate
+            (np.array([g.m], np.int64), np.array([1], np.int32)),           # id range
+            (np.array([-1], np.int64), np.array([1], np.int32)),            # id range
+            (np.array([5], np.int64), np.array([-4], np.int32)),            # negative
+            (np.array([5], np.int64), np.array([F.cap_limit + 1], np.int32)),
+        ]
+        for ids, new in bad:
+            with pytest.raises(mf.MfError) as ei:
+                F.update(ids, new)
+            assert ei.value.code == mf.MF_EINVAL
+            after = F.export_state()
+            for a, b in zip(before, after):
+                assert np.array_equal(a, b)
+            assert F.value() == v
+        # an empty batch is a no-op
+        assert F.update(np.zeros(0, np.int64), np.zeros(0, np.int32)) == v
+
+
+def test_iteration_limit_and_resume(mf):
+    g = W.seg_grid(64, seed=3)
+    with mf.MaxFlow(g, max_iterations=1) as F:
+        with pytest.raises(mf.MfError) as ei:
+            F.solve()
+        assert ei.value.code == mf.MF_ETIMEOUT
+        with pytest.raises(mf.MfError):
+            F.value()
+        F.set_max_iterations(-1)
+        F.resume()
+        check_solved(F, g, g.cap)
+
+
+# ---------------- degenerate graphs ----------------
+
+@pytest.mark.parametrize("case", ["no_out_of_s", "t_unreachable", "zero_caps", "only_loops",
+                                  "direct_edge", "two_vertices_empty"])
+def test_degenerate(mf, case):
+    if case == "no_out_of_s":
+        g = from_edges(4, [(1, 2, 5), (2, 3, 5)], 0, 3)
+    elif case == "t_unreachable":
+        g = from_edges(4, [(0, 1, 5), (1, 2, 5)], 0, 3)
+    elif case == "zero_caps":
+        g = from_edges(4, [(0, 1, 0), (1, 3, 0), (0, 3, 0)], 0, 3)
+    elif case == "only_loops":
+        g = from_edges(3, [(0, 0, 5), (1, 1, 5), (2, 2, 7)], 0, 2)
+    elif case == "direct_edge":
+        g = from_edges(2, [(0, 1, 9), (0, 1, 4), (1, 0, 3)], 0, 1)
+    else:
+        g = from_edges(2, [], 0, 1)
+    with mf.MaxFlow(g) as F:
+        F.solve()
+        check_solved(F, g, g.cap)
+        if g.m:
+            ids = np.arange(g.m, dtype=np.int64)
+            new = (np.arange(g.m) % 3 + 1).astype(np.int32)
+            F.update(ids, new)
+            cap = g.cap.copy()
+            cap[ids] = new
+            check_solved(F, g, cap)
+
+
+def test_hubs_long_lists(mf):
+    """Vertices with lists longer than one lane's share and than one BFS item
+    (hub s, hub t and an inner hub of degree 3000)."""
+    rng = np.random.default_rng(8)
+    n = 4000
+    hub = 7
+    edges = [(0, v, int(rng.integers(1, 50))) for v in range(2, n)]
+    edges += [(v, 1, int(rng.integers(1, 50))) for v in range(2, n, 2)]
+    edges += [(v, hub, int(rng.integers(1, 50))) for v in range(3, n, 2)]
+    edges += [(hub, v, int(rng.integers(1, 50))) for v in range(2, n, 4)]
+    g = from_edges(n, edges, 0, 1)
+    for grid in (1, 16):
+        with mf.MaxFlow(g, grid_blocks=grid) as F:
+            F.solve()
+            check_solved(F, g, g.cap)
+            ids, new = W.mixed_batch(g.cap, 2000, 50, np.random.default_rng(grid))
+            cap = W.apply_batch(g.cap, ids, new)
+            F.update(ids, new)
+            check_solved(F, g, cap)
+
+
+def test_repeat_runs_identical_value_and_cut(mf):
+    g = W.seg_grid(128, seed=11)
+    value, side, _ = O.dinic(g)
+    for rep in range(4):
+        with mf.MaxFlow(g, grid_blocks=[0, 4, 32, 1][rep]) as F:
+            assert F.solve() == value
+            assert np.array_equal(F.min_cut()[0], side)
