@@ -71,7 +71,14 @@ typedef struct {
                                per call; < 0 unlimited (default)            */
     int32_t time_budget_ms; /* wall time one solve launch may take before it
                                stops with MF_ETIMEOUT (resumable); 0 = 60 s */
-    int32_t reserved[7];    /* must be zero                                   */
+    int32_t max_rounds;     /* push/relabel rounds between two global relabels;
+                               0 = 65536                                     */
+    int32_t relabel_budget; /* relabels allowed between two global relabels
+                               before the next one is forced; 0 = max(1024, n/2) */
+    int32_t rounds_per_level; /* a phase also ends after this many rounds per
+                               level of the BFS that began it (+16); 0 = 2,
+                               < 0 = no such cap                             */
+    int32_t reserved[4];    /* must be zero                                   */
 } mf_opts_t;
 
 /* Counters of the last mf_solve / mf_apply_updates* / mf_resume call. */
@@ -90,8 +97,12 @@ typedef struct {
     int64_t updates;          /* edge updates applied                         */
     int64_t clamps;           /* arcs whose flow was clamped to a new capacity */
     int64_t source_pushes;    /* arcs out of s saturated                      */
+    int64_t rounds;           /* push/relabel rounds                          */
     int64_t loop_launches;    /* launches of the persistent solve kernel      */
     int64_t grid_blocks;      /* workgroups of that kernel                    */
+    double bfs_ms;            /* device wall time in global relabels          */
+    double pr_ms;             /* ... in push/relabel rounds                   */
+    double rie_ms;            /* ... in RemoveInvalidEdges                    */
     double loop_kernel_ms;    /* HIP-event time of the solve kernel launches  */
     double call_ms;           /* HIP-event time of the whole call's GPU work  */
 } mf_stats_t;

@@ -41,6 +41,11 @@ struct mf_handle {
     int64_t max_iter = -1;
     int64_t deadline_ticks = 0;
     int64_t barrier_ticks = 0;
+    int64_t relabel_budget = 0;
+    int32_t max_rounds = 0;
+    int32_t rounds_per_level = 2;
+    double tick_ms = 1e-5;  // one wall-clock tick in ms
+    int32_t seq = 1;  // next round id; round ids stamp mark[] and rmark[]
     int32_t epoch = 0;
     State state = State::NoFlow;
     int64_t value = 0;
@@ -118,7 +123,11 @@ void fill_stats(mf_handle_t *h, bool ran_loop) {
     s.updates = c.stat[mf::kStUpdates];
     s.clamps = c.stat[mf::kStClamps];
     s.source_pushes = c.stat[mf::kStSourcePushes];
+    s.rounds = c.stat[mf::kStRounds];
     s.grid_blocks = h->grid;
+    s.bfs_ms = c.stat[mf::kStBfsTicks] * h->tick_ms;
+    s.pr_ms = c.stat[mf::kStPrTicks] * h->tick_ms;
+    s.rie_ms = c.stat[mf::kStRieTicks] * h->tick_ms;
     if (ran_loop) {
         float ms = 0.f;
         s.loop_launches = 1;
@@ -130,7 +139,13 @@ void fill_stats(mf_handle_t *h, bool ran_loop) {
 
 // Launch the persistent loop, read back, interpret the status.
 int run_loop_and_finish(mf_handle_t *h) {
-    mf::LoopParams p{h->kc, h->mode, h->max_iter, h->deadline_ticks, h->barrier_ticks};
+    if (h->seq > (1 << 30)) {  // keep round ids unique: restart them with clean stamps
+        HIP_TRY(h, mf::launch_fill_i32(h->g.mark, h->g.n, 0, h->stream));
+        HIP_TRY(h, mf::launch_fill_i32(h->g.rmark, h->g.n, 0, h->stream));
+        h->seq = 1;
+    }
+    mf::LoopParams p{h->kc, h->mode, h->max_iter, h->deadline_ticks, h->barrier_ticks,
+                     h->relabel_budget, h->max_rounds, h->seq, h->rounds_per_level, 0};
     HIP_TRY(h, hipEventRecord(h->ev[1], h->stream));
     HIP_TRY(h, mf::launch_loop(h->g, p, h->grid, h->stream));
     HIP_TRY(h, hipEventRecord(h->ev[2], h->stream));
@@ -138,6 +153,7 @@ int run_loop_and_finish(mf_handle_t *h) {
     if (rc) return rc;
     const mf::Ctrl &c = *h->h_ctrl;
     if (c.err) return MF_EINVAL;  // caller reports the message
+    h->seq += c.rounds + 1;
     fill_stats(h, true);
     if (c.status == mf::kSolved) {
         h->state = State::Solved;
@@ -216,7 +232,9 @@ bool opts_valid(const mf_opts_t &o, std::string *why) {
     if (o.grid_blocks < 0) { *why = "grid_blocks must be >= 0"; return false; }
     if (o.device < 0) { *why = "device must be >= 0"; return false; }
     if (o.time_budget_ms < 0) { *why = "time_budget_ms must be >= 0"; return false; }
-    for (int i = 0; i < 7; ++i)
+    if (o.max_rounds < 0) { *why = "max_rounds must be >= 0"; return false; }
+    if (o.relabel_budget < 0) { *why = "relabel_budget must be >= 0"; return false; }
+    for (int i = 0; i < 4; ++i)
         if (o.reserved[i]) { *why = "reserved fields must be zero"; return false; }
     return true;
 }
@@ -286,6 +304,9 @@ MF_API int mf_create(const mf_csr_t *g, const int32_t *cap, int32_t s, int32_t t
     h->mode = o.mode;
     h->max_iter = o.max_iterations;
     const int64_t budget_ms = o.time_budget_ms > 0 ? o.time_budget_ms : 60000;
+    h->max_rounds = o.max_rounds > 0 ? o.max_rounds : 65536;
+    h->relabel_budget = o.relabel_budget > 0 ? o.relabel_budget : std::max<int64_t>(1024, n / 2);
+    h->rounds_per_level = o.rounds_per_level == 0 ? 2 : (o.rounds_per_level < 0 ? 0 : o.rounds_per_level);
     h->kc = o.kernel_cycles > 0 ? o.kernel_cycles
                                 : (int32_t)std::max<int64_t>(1, (int64_t)((double)m / n + 0.5));
     auto bail = [&](int code, const std::string &msg) {
@@ -334,8 +355,13 @@ MF_API int mf_create(const mf_csr_t *g, const int32_t *cap, int32_t s, int32_t t
     ALLOC(d.h, n);
     ALLOC(d.q[0], d.qcap);
     ALLOC(d.q[1], d.qcap);
-    ALLOC(d.wl_light, n);
-    ALLOC(d.wl_heavy, n);
+    ALLOC(d.list[0], n);
+    ALLOC(d.list[1], n);
+    ALLOC(d.list[2], n);
+    ALLOC(d.mark, n);
+    ALLOC(d.rmark, n);
+    ALLOC(d.relab, n);
+    ALLOC(d.cur, n);
     ALLOC(d.heavy_all, (int64_t)heavy.size());
     ALLOC(d.ctrl, 1);
     ALLOC(h->d_side, n);
@@ -355,6 +381,9 @@ MF_API int mf_create(const mf_csr_t *g, const int32_t *cap, int32_t s, int32_t t
         (e = up(d.heavy_all, heavy.data(), sizeof(int32_t) * heavy.size())) != hipSuccess)
         return bail(MF_EDEVICE, std::string("upload: ") + hipGetErrorString(e));
     if ((e = mf::launch_fill_i32(d.stamp, m, 0, h->stream)) != hipSuccess ||
+        (e = mf::launch_fill_i32(d.mark, n, 0, h->stream)) != hipSuccess ||
+        (e = mf::launch_fill_i32(d.rmark, n, 0, h->stream)) != hipSuccess ||
+        (e = mf::launch_fill_i32(d.cur, n, 0, h->stream)) != hipSuccess ||
         (e = mf::launch_reset_ctrl(d, h->stream)) != hipSuccess ||
         (e = hipStreamSynchronize(h->stream)) != hipSuccess)
         return bail(MF_EDEVICE, std::string("init: ") + hipGetErrorString(e));
@@ -364,15 +393,22 @@ MF_API int mf_create(const mf_csr_t *g, const int32_t *cap, int32_t s, int32_t t
         clock_khz <= 0)
         clock_khz = 100000;
     h->deadline_ticks = budget_ms * (int64_t)clock_khz;
+    h->tick_ms = 1.0 / clock_khz;
     h->barrier_ticks = 10000 * (int64_t)clock_khz;  // 10 s
     // workgroups of the persistent kernel
     int maxb = 0;
     if ((e = mf::loop_max_coresident(o.device, &maxb)) != hipSuccess)
         return bail(MF_EDEVICE, std::string("occupancy query: ") + hipGetErrorString(e));
+    // one workgroup for small graphs (no grid barrier at all); otherwise about
+    // one 1024-thread workgroup per 64K arcs, at most one per compute unit:
+    // a grid barrier costs roughly 60 ns per participating workgroup
+    int cus = 0;
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, o.device);
     int grid = o.grid_blocks;
     if (grid == 0) {
-        if ((int64_t)n <= 4096 && A <= (1 << 16)) grid = 1;
-        else grid = (int)std::min<int64_t>(maxb, std::max<int64_t>(8, ((int64_t)n + 511) / 512));
+        if ((int64_t)n <= 8192 && A <= (1 << 17)) grid = 1;
+        else grid = (int)std::min<int64_t>(std::min(maxb, std::max(cus, 1)),
+                                           std::max<int64_t>(8, (A + 65535) / 65536));
     }
     if (grid > 1 && grid > maxb)
         return bail(MF_EINVAL, "grid_blocks above the co-resident limit " + std::to_string(maxb));

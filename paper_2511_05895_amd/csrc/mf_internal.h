@@ -13,10 +13,8 @@ constexpr int kLightMaxDeg = 32;
 // Arcs per BFS frontier item: a frontier vertex with a longer list is split
 // into several items so that hubs are expanded by many wavefronts at once.
 constexpr int kChunk = 256;
-// Threads per workgroup of the multi-workgroup persistent kernel and of the
-// one-workgroup variant.
-constexpr int kBlock = 256;
-constexpr int kBlockSingle = 1024;
+// Threads per workgroup of the persistent solve kernel.
+constexpr int kBlock = 1024;
 
 // Loop status written by the persistent kernel.
 enum : int32_t { kRunning = 0, kSolved = 1, kIterLimit = 2, kAborted = 3, kDeadline = 4 };
@@ -37,12 +35,26 @@ enum : int {
     kStClamps,
     kStSourcePushes,
     kStIterations,
+    kStRounds,
+    kStBfsTicks,
+    kStPrTicks,
+    kStRieTicks,
     kStCount
 };
 
 struct alignas(128) PaddedU32 {
     uint32_t v;
     uint32_t pad[31];
+};
+
+// One active-vertex list of the push/relabel rounds: vertices with short arc
+// lists fill items[0, light) from the front, the others items[n-heavy, n) from
+// the back; `grab` hands out the long-list vertices to wavefronts.
+struct ListCtr {
+    int32_t light;
+    int32_t heavy;
+    int32_t grab;
+    int32_t pad;
 };
 
 // Device control block: barrier words on their own cache lines, then loop
@@ -52,12 +64,14 @@ struct Ctrl {
     PaddedU32 bar_gen;
     PaddedU32 abort;
     int32_t qcount[4];  // frontier items per BFS level, triple-buffered
-    int32_t nlight;     // active vertices with short arc lists
-    int32_t nheavy;     // active vertices with long arc lists
+    ListCtr lst[3];     // active lists of the rounds, triple-buffered
+    int32_t nrelab;     // vertices relabelled in the current phase
     int32_t status;
     int32_t err;        // update validation: 1 id range, 2 capacity range, 4 duplicate
     int32_t stop;       // set by the leader when the time budget ran out
+    int32_t rounds;     // push/relabel rounds run by this call (round ids)
     int32_t pad_;
+    int64_t phase_relabels;  // relabels of the current phase
     int64_t deficit;    // sum of e(v) < 0 over v not in {s, t} at termination
     int64_t e_t;        // e(t) at termination
     int64_t cut;        // cut capacity (k_min_cut)
@@ -80,19 +94,28 @@ struct DevGraph {
     int32_t *h;         // n
     int2 *q[2];         // BFS frontier items {vertex, first arc}, double-buffered
     int64_t qcap;       // items per frontier buffer
-    int32_t *wl_light;  // n
-    int32_t *wl_heavy;  // n
+    int32_t *list[3];   // n each: active lists of the push/relabel rounds
+    int32_t *mark;      // n: id of the round list a vertex was last added to
+    int32_t *rmark;     // n: id of the phase a vertex last relabelled in
+    int32_t *relab;     // n: vertices relabelled in the current phase
+    int32_t *cur;       // n: current arc of each vertex (offset in its list)
     int32_t *heavy_all; // vertices with long arc lists (topology-driven sweeps)
     int32_t n_heavy_all;
     Ctrl *ctrl;
 };
 
 struct LoopParams {
-    int32_t kc;              // KERNELCYCLES
+    int32_t kc;              // KERNELCYCLES: push/relabel operations per vertex visit
     int32_t mode;            // 0 data-driven, 1 topology-driven
     int64_t max_iter;        // < 0 unlimited
     int64_t deadline_ticks;  // wall-clock ticks allowed for one launch (> 0)
     int64_t barrier_ticks;   // wall-clock ticks one grid-barrier wait may take
+    int64_t relabel_budget;  // relabels allowed per phase before a global relabel
+    int32_t max_rounds;      // push/relabel rounds allowed per phase
+    int32_t seq_base;        // first round id of this call (marks stay unique)
+    int32_t rounds_per_level;  // > 0: a phase also stops after this many rounds per
+                               // level of the BFS that started it (+16)
+    int32_t pad_;
 };
 
 // ---- launch wrappers (mf_kernels.hip) ----
@@ -107,7 +130,7 @@ hipError_t launch_clamp(const DevGraph &g, const int64_t *ids, int64_t k, hipStr
 hipError_t launch_loop(const DevGraph &g, const LoopParams &p, int grid, hipStream_t st);
 hipError_t launch_min_cut(const DevGraph &g, uint8_t *d_side, hipStream_t st);
 hipError_t launch_fill_i32(int32_t *p, int64_t count, int32_t value, hipStream_t st);
-// Largest co-resident workgroup count of the multi-workgroup loop kernel.
+// Largest co-resident workgroup count of the loop kernel.
 hipError_t loop_max_coresident(int device, int *blocks);
 
 }  // namespace mf

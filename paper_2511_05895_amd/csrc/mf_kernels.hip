@@ -36,27 +36,45 @@ namespace mf {
 
 __device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
 
-__device__ __forceinline__ int32_t ld_dev(const int32_t *p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// Scoped atomics.  The one-workgroup solve kernel works at workgroup scope
+// (atomics resolve in the compute unit's own caches); the multi-workgroup
+// kernel and the update kernels need device scope, because gfx950 spreads a
+// grid over eight XCDs with separate L2 caches.
+constexpr int kAgent = __HIP_MEMORY_SCOPE_AGENT;
+constexpr int kGroup = __HIP_MEMORY_SCOPE_WORKGROUP;
+
+template <int SC>
+__device__ __forceinline__ int32_t ld(const int32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, SC);
 }
-__device__ __forceinline__ int64_t ld_dev(const int64_t *p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+template <int SC>
+__device__ __forceinline__ int64_t ld(const int64_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, SC);
 }
-__device__ __forceinline__ void add_dev(int32_t *p, int32_t v) {
-    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+template <int SC>
+__device__ __forceinline__ void add(int32_t *p, int32_t v) {
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, SC);
 }
-__device__ __forceinline__ void add_dev(int64_t *p, int64_t v) {
-    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+template <int SC>
+__device__ __forceinline__ void add(int64_t *p, int64_t v) {
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, SC);
 }
-__device__ __forceinline__ int32_t fetch_add_dev(int32_t *p, int32_t v) {
-    return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+template <int SC>
+__device__ __forceinline__ int32_t fetch_add(int32_t *p, int32_t v) {
+    return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, SC);
 }
-__device__ __forceinline__ int32_t xchg_dev(int32_t *p, int32_t v) {
-    return __hip_atomic_exchange(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+template <int SC>
+__device__ __forceinline__ int64_t fetch_add(int64_t *p, int64_t v) {
+    return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, SC);
 }
-__device__ __forceinline__ bool cas_dev(int32_t *p, int32_t expected, int32_t desired) {
+template <int SC>
+__device__ __forceinline__ int32_t xchg(int32_t *p, int32_t v) {
+    return __hip_atomic_exchange(p, v, __ATOMIC_RELAXED, SC);
+}
+template <int SC>
+__device__ __forceinline__ bool cas(int32_t *p, int32_t expected, int32_t desired) {
     return __hip_atomic_compare_exchange_strong(p, &expected, desired, __ATOMIC_RELAXED,
-                                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                                                __ATOMIC_RELAXED, SC);
 }
 
 // residual capacity field of arc a
@@ -96,24 +114,26 @@ __device__ __forceinline__ int mask_rank(uint64_t mask) {
 
 // Reserve one slot per lane with pred; one atomic per wavefront.  Every lane
 // of the wavefront must call it.  Returns the slot, or -1 without pred.
+template <int SC>
 __device__ __forceinline__ int wave_append1(int32_t *counter, bool pred) {
     uint64_t mask = __ballot(pred);
     if (mask == 0) return -1;
     int leader = __ffsll((unsigned long long)mask) - 1;
     int base = 0;
-    if (lane_id() == leader) base = fetch_add_dev(counter, __popcll(mask));
+    if (lane_id() == leader) base = fetch_add<SC>(counter, __popcll(mask));
     base = __shfl(base, leader, 64);
     return pred ? base + mask_rank(mask) : -1;
 }
 
 // Reserve c slots per lane (c >= 0); one atomic per wavefront.  Every lane must
 // call it.  Returns the first slot of this lane's range.
+template <int SC>
 __device__ __forceinline__ int wave_appendn(int32_t *counter, int c) {
     int incl = wave_incl_scan(c);
     int total = __shfl(incl, 63, 64);
     if (total == 0) return 0;
     int base = 0;
-    if (lane_id() == 63) base = fetch_add_dev(counter, total);
+    if (lane_id() == 63) base = fetch_add<SC>(counter, total);
     base = __shfl(base, 63, 64);
     return base + incl - c;
 }
@@ -164,26 +184,29 @@ __device__ bool grid_barrier(Ctrl *c, int64_t limit) {
     return s_ok != 0;
 }
 
-// Per-thread event counters, summed into Ctrl::stat at kernel end.
+// Per-thread event counters (32-bit), summed into the 64-bit Ctrl::stat at the
+// end of every loop round and of the kernel, then cleared.
 struct Tally {
-    int64_t bfs_v = 0, bfs_a = 0, pr_cyc = 0, pr_a = 0, push = 0, relabel = 0, rie_a = 0, rie_sat = 0;
+    uint32_t bfs_v = 0, bfs_a = 0, pr_cyc = 0, pr_a = 0, push = 0, relabel = 0, rie_a = 0, rie_sat = 0;
 };
 
-template <int BLOCK>
-__device__ void flush_tally(Ctrl *c, const Tally &t) {
+// Every thread of the workgroup must call it.
+template <int SC>
+__device__ void flush_tally(Ctrl *c, Tally &t) {
     __shared__ int64_t s_acc[8];
     if (threadIdx.x < 8) s_acc[threadIdx.x] = 0;
     __syncthreads();
-    int64_t v[8] = {t.bfs_v, t.bfs_a, t.pr_cyc, t.pr_a, t.push, t.relabel, t.rie_a, t.rie_sat};
+    const uint32_t v[8] = {t.bfs_v, t.bfs_a, t.pr_cyc, t.pr_a, t.push, t.relabel, t.rie_a, t.rie_sat};
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
-        int64_t w = wave_sum(v[i]);
+        const int64_t w = wave_sum((int64_t)v[i]);
         if (lane_id() == 0 && w) atomicAdd((unsigned long long *)&s_acc[i], (unsigned long long)w);
     }
     __syncthreads();
     const int slot[8] = {kStBfsVertices, kStBfsArcs, kStPrCycles, kStPrArcs,
                          kStPushes,      kStRelabels, kStRieArcs, kStRieSat};
-    if (threadIdx.x < 8 && s_acc[threadIdx.x]) add_dev(&c->stat[slot[threadIdx.x]], s_acc[threadIdx.x]);
+    if (threadIdx.x < 8 && s_acc[threadIdx.x]) add<SC>(&c->stat[slot[threadIdx.x]], s_acc[threadIdx.x]);
+    t = Tally{};
 }
 
 // ---------------------------------------------------------------------------
@@ -192,6 +215,7 @@ __device__ void flush_tally(Ctrl *c, const Tally &t) {
 
 // Height reset: t and every deficient vertex other than s are roots (height
 // 0); all others get |V|.  Roots become the level-0 frontier.
+template <int SC>
 __device__ void bfs_roots(const DevGraph &g, Tally &tl) {
     const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -209,7 +233,7 @@ __device__ void bfs_roots(const DevGraph &g, Tally &tl) {
             }
         }
         const int c = root ? n_items(deg) : 0;
-        const int base = wave_appendn(&g.ctrl->qcount[0], c);
+        const int base = wave_appendn<SC>(&g.ctrl->qcount[0], c);
         for (int j = 0; j < c; ++j) g.q[0][base + j] = make_int2(v, beg + j * kChunk);
         tl.bfs_v += root;
     }
@@ -220,10 +244,11 @@ __device__ void bfs_roots(const DevGraph &g, Tally &tl) {
 // capacity toward w (the twin arc v -> w).  Newly reached vertices become
 // frontier items of the next level; those with positive excess go to the
 // active worklist (A of Alg. 1: e > 0 and h < |V|, s and t excluded).
+template <int SC>
 __device__ void bfs_level(const DevGraph &g, int L, Tally &tl) {
     const int2 *__restrict__ qin = g.q[L & 1];
     int2 *qout = g.q[(L + 1) & 1];
-    const int cnt = ld_dev(&g.ctrl->qcount[L % 3]);
+    const int cnt = ld<SC>(&g.ctrl->qcount[L % 3]);
     int32_t *qout_count = &g.ctrl->qcount[(L + 1) % 3];
     const int lane = lane_id();
     const int64_t wpb = blockDim.x >> 6;
@@ -262,7 +287,7 @@ __device__ void bfs_level(const DevGraph &g, int L, Tally &tl) {
                 tl.bfs_a++;
                 if (v != g.s && g.h[v] == n) {
                     const int tw = g.twin[a];
-                    if (g.arc[tw].y > 0) disc = cas_dev(&g.h[v], n, L + 1);
+                    if (g.arc[tw].y > 0) disc = cas<SC>(&g.h[v], n, L + 1);
                 }
             }
             int vbeg = 0, vdeg = 0;
@@ -274,193 +299,311 @@ __device__ void bfs_level(const DevGraph &g, int L, Tally &tl) {
                 tl.bfs_v++;
             }
             const int c = disc ? n_items(vdeg) : 0;
-            const int qb = wave_appendn(qout_count, c);
+            const int qb = wave_appendn<SC>(qout_count, c);
             for (int k = 0; k < c; ++k) qout[qb + k] = make_int2(v, vbeg + k * kChunk);
             const bool light = active && vdeg <= kLightMaxDeg;
             const bool heavy = active && vdeg > kLightMaxDeg;
-            const int sl = wave_append1(&g.ctrl->nlight, light);
-            if (light) g.wl_light[sl] = v;
-            const int sh = wave_append1(&g.ctrl->nheavy, heavy);
-            if (heavy) g.wl_heavy[sh] = v;
+            const int sl = wave_append1<SC>(&g.ctrl->lst[0].light, light);
+            if (light) g.list[0][sl] = v;
+            const int sh = wave_append1<SC>(&g.ctrl->lst[0].heavy, heavy);
+            if (heavy) g.list[0][n - 1 - sh] = v;
         }
     }
 }
 
 // ---------------------------------------------------------------------------
-// PushRelabel (Alg. 2)
+// PushRelabel (Alg. 2), run in rounds
+//
+// A phase between two global relabels runs rounds.  Round r processes the
+// vertices of list r; a vertex whose excess turns positive through a push, or
+// that keeps excess after its visit, is added once (round-id stamp) to list
+// r+1.  So excess can travel many arcs between global relabels instead of one
+// arc per relabel.  A phase ends when a list is empty, or when the relabel
+// budget or the round cap is spent; the next global relabel then restarts from
+// exact heights.
+//
+// One cycle (KERNELCYCLES counts cycles) scans the arcs for the lowest residual
+// neighbour height h^; if h(u) > h^ it pushes along the arcs at height h^ in
+// arc order until the excess is gone (the paper's cycles pick the lowest arc,
+// first in arc order, one push each; with the same h^ the next cycles would
+// take exactly these arcs), otherwise it relabels h(u) = h^ + 1.
 // ---------------------------------------------------------------------------
 
-// One lane per vertex.  Every lane of the wavefront runs all kc cycles so the
-// wavefront stays converged for the aggregated excess update of t.
-__device__ void push_relabel_lanes(const DevGraph &g, const int32_t *list, int64_t count,
-                                   bool topology, int kc, Tally &tl) {
+struct RoundCtx {
+    int32_t *next;     // list of the next round
+    ListCtr *next_ctr;
+    int32_t next_id;   // round id stamped into mark[] for that list
+    int32_t phase_id;  // stamped into rmark[] on a vertex's first relabel
+};
+
+// Add v to the next round's list unless it is already there.
+template <int SC>
+__device__ __forceinline__ void list_add(const DevGraph &g, const RoundCtx &rc, int v) {
+    if (xchg<SC>(&g.mark[v], rc.next_id) == rc.next_id) return;
+    const int deg = g.row_ptr[v + 1] - g.row_ptr[v];
+    if (deg <= kLightMaxDeg) {
+        const int slot = fetch_add<SC>(&rc.next_ctr->light, 1);
+        rc.next[slot] = v;
+    } else {
+        const int slot = fetch_add<SC>(&rc.next_ctr->heavy, 1);
+        rc.next[g.n - 1 - slot] = v;
+    }
+}
+
+// First relabel of u in this phase: remember u for RemoveInvalidEdges.  Only
+// the one lane (or wavefront) visiting u in a round touches rmark[u].
+template <int SC>
+__device__ __forceinline__ void note_relabel(const DevGraph &g, int u, int32_t phase_id) {
+    if (g.rmark[u] != phase_id) {
+        g.rmark[u] = phase_id;
+        const int slot = fetch_add<SC>(&g.ctrl->nrelab, 1);
+        g.relab[slot] = u;
+    }
+}
+
+// Push d from u along arc a to v = head(a).  Residual capacity moves to the
+// twin; excess moves from u to v except that the excess taken from u is
+// subtracted by the caller (one atomic per visit chunk).
+template <int SC>
+__device__ __forceinline__ void push_arc(const DevGraph &g, const RoundCtx &rc, int a, int v,
+                                         int32_t d, int64_t &to_t) {
+    add<SC>(cf_ptr(g.arc, a), -d);
+    add<SC>(cf_ptr(g.arc, g.twin[a]), d);
+    if (v == g.t) {
+        to_t += d;
+    } else {
+        const int64_t old = fetch_add<SC>(&g.e[v], (int64_t)d);
+        if (old <= 0 && old + d > 0 && v != g.s) list_add<SC>(g, rc, v);
+    }
+}
+
+// One lane visits vertex u.  Returns the number of relabels.
+template <int SC>
+__device__ int discharge_lane(const DevGraph &g, int u, int kc, const RoundCtx &rc, Tally &tl,
+                              int64_t &to_t) {
+    const int n = g.n;
+    const int beg = g.row_ptr[u], end = g.row_ptr[u + 1];
+    int hu = g.h[u];
+    int relabels = 0;
+    for (int cyc = 0; cyc < kc && hu < n; ++cyc) {
+        int64_t eu = ld<SC>(&g.e[u]);
+        if (eu <= 0) break;
+        tl.pr_cyc++;
+        int hmin = INT32_MAX;
+        for (int a = beg; a < end; ++a) {
+            const int2 r = g.arc[a];
+            if (r.y > 0) hmin = min(hmin, g.h[r.x]);
+        }
+        tl.pr_a += end - beg;
+        if (hmin == INT32_MAX) break;
+        if (hu > hmin) {
+            int64_t sent = 0;
+            for (int a = beg; a < end && sent < eu; ++a) {
+                const int2 r = g.arc[a];
+                if (r.y <= 0 || g.h[r.x] != hmin) continue;
+                const int32_t cfl = ld<SC>(cf_ptr(g.arc, a));
+                const int64_t d = min(eu - sent, (int64_t)cfl);
+                if (d <= 0) continue;
+                push_arc<SC>(g, rc, a, r.x, (int32_t)d, to_t);
+                sent += d;
+                tl.push++;
+            }
+            if (sent) add<SC>(&g.e[u], -sent);
+        } else {
+            hu = hmin + 1;
+            g.h[u] = hu;
+            tl.relabel++;
+            relabels++;
+            note_relabel<SC>(g, u, rc.phase_id);
+        }
+    }
+    if (hu < n && ld<SC>(&g.e[u]) > 0) list_add<SC>(g, rc, u);
+    return relabels;
+}
+
+// One wavefront visits vertex u (long arc list).  Lanes scan the arcs; the
+// push pass hands the excess to the lowest arcs in arc order with a wavefront
+// prefix sum of their residual capacities.  Returns relabels (on lane 0).
+template <int SC>
+__device__ int discharge_wave(const DevGraph &g, int u, int kc, const RoundCtx &rc, Tally &tl,
+                              int64_t &to_t) {
+    const int lane = lane_id();
+    const int n = g.n;
+    const int beg = g.row_ptr[u], end = g.row_ptr[u + 1];
+    int hu = g.h[u];
+    int relabels = 0;
+    for (int cyc = 0; cyc < kc && hu < n; ++cyc) {
+        int64_t eu = 0;
+        if (lane == 0) eu = ld<SC>(&g.e[u]);
+        eu = __shfl(eu, 0, 64);
+        if (eu <= 0) break;
+        if (lane == 0) tl.pr_cyc++;
+        int hmin = INT32_MAX;
+        for (int a = beg + lane; a < end; a += 64) {
+            const int2 r = g.arc[a];
+            if (r.y > 0) hmin = min(hmin, g.h[r.x]);
+        }
+        if (lane == 0) tl.pr_a += end - beg;
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) hmin = min(hmin, __shfl_xor(hmin, d, 64));
+        if (hmin == INT32_MAX) break;
+        if (hu > hmin) {
+            int64_t sent = 0;
+            for (int base = beg; base < end && sent < eu; base += 64) {
+                const int a = base + lane;
+                int64_t c = 0;
+                int v = -1;
+                if (a < end) {
+                    const int2 r = g.arc[a];
+                    if (r.y > 0 && g.h[r.x] == hmin) {
+                        c = max(0, ld<SC>(cf_ptr(g.arc, a)));
+                        v = r.x;
+                    }
+                }
+                // inclusive prefix sum of c over the wavefront, in arc order
+                int64_t incl = c;
+#pragma unroll
+                for (int d = 1; d < 64; d <<= 1) {
+                    const int64_t y = __shfl_up(incl, d, 64);
+                    if (lane >= d) incl += y;
+                }
+                const int64_t room = eu - sent;
+                const int64_t excl = incl - c;
+                const int64_t d = (c > 0 && excl < room) ? min(c, room - excl) : 0;
+                if (d > 0) {
+                    push_arc<SC>(g, rc, a, v, (int32_t)d, to_t);
+                    tl.push++;
+                }
+                const int64_t tot = min(__shfl(incl, 63, 64), room);
+                sent += tot;
+            }
+            if (lane == 0 && sent) add<SC>(&g.e[u], -sent);
+        } else {
+            hu = hmin + 1;
+            relabels++;
+            if (lane == 0) {
+                g.h[u] = hu;
+                tl.relabel++;
+                note_relabel<SC>(g, u, rc.phase_id);
+            }
+        }
+    }
+    if (lane == 0 && hu < n && ld<SC>(&g.e[u]) > 0) list_add<SC>(g, rc, u);
+    return lane == 0 ? relabels : 0;
+}
+
+// Excess pushed into t by the lanes of a wavefront, added with one atomic.
+template <int SC>
+__device__ __forceinline__ void flush_to_t(const DevGraph &g, int64_t &to_t) {
+    const int64_t s = wave_sum(to_t);
+    if (lane_id() == 0 && s) add<SC>(&g.e[g.t], s);
+    to_t = 0;
+}
+
+template <int SC>
+__device__ __forceinline__ void flush_relabels(Ctrl *c, int64_t &rl) {
+    const int64_t s = wave_sum(rl);
+    if (lane_id() == 0 && s) add<SC>(&c->phase_relabels, s);
+    rl = 0;
+}
+
+// One data-driven round over list rd: short lists by lane, long ones by
+// wavefronts that take the next vertex from a shared counter.
+template <int SC>
+__device__ void pr_round(const DevGraph &g, int rd, int nl, int nh, int kc, const RoundCtx &rc,
+                         Tally &tl) {
     const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    const int64_t cr = (count + 63) & ~63ll;
-    const int n = g.n;
-    const int lane = lane_id();
-    for (int64_t i = gtid; i < cr; i += stride) {
-        int u = -1, beg = 0, end = 0, hu = n;
-        if (i < count) {
-            u = topology ? (int)i : list[i];
-            beg = g.row_ptr[u];
-            end = g.row_ptr[u + 1];
-            if (topology && (end - beg > kLightMaxDeg || u == g.s || u == g.t)) u = -1;
-            if (u >= 0) hu = g.h[u];
-        }
-        for (int cyc = 0; cyc < kc; ++cyc) {
-            bool act = u >= 0 && hu < n;
-            int64_t eu = 0;
-            if (act) {
-                eu = ld_dev(&g.e[u]);
-                act = eu > 0;
-            }
-            int tgt = -1;
-            int64_t d = 0;
-            if (act) {
-                tl.pr_cyc++;
-                uint64_t best = ~0ull;
-                for (int a = beg; a < end; ++a) {
-                    const int2 r = g.arc[a];
-                    if (r.y > 0) {
-                        const uint64_t key = ((uint64_t)(uint32_t)g.h[r.x] << 32) | (uint32_t)a;
-                        best = key < best ? key : best;
-                    }
-                }
-                tl.pr_a += end - beg;
-                if (best != ~0ull) {
-                    const int hh = (int)(best >> 32);
-                    const int ah = (int)(uint32_t)best;
-                    if (hu > hh) {
-                        int32_t *cfa = cf_ptr(g.arc, ah);
-                        const int32_t cfl = ld_dev(cfa);
-                        d = eu < (int64_t)cfl ? eu : (int64_t)cfl;
-                        if (d > 0) {
-                            add_dev(cfa, -(int32_t)d);
-                            add_dev(cf_ptr(g.arc, g.twin[ah]), (int32_t)d);
-                            add_dev(&g.e[u], -d);
-                            tgt = g.arc[ah].x;
-                            tl.push++;
-                        }
-                    } else {
-                        hu = hh + 1;
-                        g.h[u] = hu;
-                        tl.relabel++;
-                    }
-                }
-            }
-            const bool to_t = tgt == g.t;
-            const uint64_t mt = __ballot(to_t);
-            if (mt) {
-                const int64_t sum = wave_sum(to_t ? d : 0);
-                if (lane == __ffsll((unsigned long long)mt) - 1) add_dev(&g.e[g.t], sum);
-            }
-            if (tgt >= 0 && !to_t) add_dev(&g.e[tgt], d);
-        }
+    const int32_t *lst = g.list[rd];
+    int64_t to_t = 0, rl = 0;
+    for (int64_t i = gtid; i < nl; i += stride) rl += discharge_lane<SC>(g, lst[i], kc, rc, tl, to_t);
+    flush_to_t<SC>(g, to_t);
+    int32_t *grab = &g.ctrl->lst[rd].grab;
+    for (;;) {
+        int idx = 0;
+        if (lane_id() == 0) idx = fetch_add<SC>(grab, 1);
+        idx = __shfl(idx, 0, 64);
+        if (idx >= nh) break;
+        rl += discharge_wave<SC>(g, lst[g.n - 1 - idx], kc, rc, tl, to_t);
     }
+    flush_to_t<SC>(g, to_t);
+    flush_relabels<SC>(g.ctrl, rl);
 }
 
-// One wavefront per vertex: lanes scan the arc list, a packed (height, arc)
-// minimum picks the lowest residual neighbour (first in arc order on ties),
-// lane 0 pushes or relabels.
-__device__ void push_relabel_waves(const DevGraph &g, const int32_t *list, int64_t count, int kc,
-                                   Tally &tl) {
-    const int lane = lane_id();
+// One topology-driven round: every vertex is visited (idle when inactive).
+template <int SC>
+__device__ void pr_round_topology(const DevGraph &g, int kc, const RoundCtx &rc, Tally &tl) {
+    const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    int64_t to_t = 0, rl = 0;
+    for (int64_t i = gtid; i < g.n; i += stride) {
+        const int u = (int)i;
+        if (u == g.s || u == g.t) continue;
+        if (g.row_ptr[u + 1] - g.row_ptr[u] > kLightMaxDeg) continue;
+        rl += discharge_lane<SC>(g, u, kc, rc, tl, to_t);
+    }
+    flush_to_t<SC>(g, to_t);
     const int64_t wpb = blockDim.x >> 6;
     const int64_t gwave = (int64_t)blockIdx.x * wpb + (threadIdx.x >> 6);
     const int64_t nwaves = (int64_t)gridDim.x * wpb;
-    const int n = g.n;
-    for (int64_t i = gwave; i < count; i += nwaves) {
-        const int u = list[i];
-        const int beg = g.row_ptr[u], end = g.row_ptr[u + 1];
-        int hu = g.h[u];
-        for (int cyc = 0; cyc < kc; ++cyc) {
-            int64_t eu = 0;
-            if (lane == 0) eu = ld_dev(&g.e[u]);
-            eu = __shfl(eu, 0, 64);
-            if (eu <= 0 || hu >= n) break;
-            if (lane == 0) tl.pr_cyc++;
-            uint64_t best = ~0ull;
-            for (int a = beg + lane; a < end; a += 64) {
-                const int2 r = g.arc[a];
-                if (r.y > 0) {
-                    const uint64_t key = ((uint64_t)(uint32_t)g.h[r.x] << 32) | (uint32_t)a;
-                    best = key < best ? key : best;
-                }
-            }
-            if (lane == 0) tl.pr_a += end - beg;
-            best = wave_min(best);
-            if (best == ~0ull) break;
-            const int hh = (int)(best >> 32);
-            const int ah = (int)(uint32_t)best;
-            if (hu > hh) {
-                if (lane == 0) {
-                    int32_t *cfa = cf_ptr(g.arc, ah);
-                    const int32_t cfl = ld_dev(cfa);
-                    const int64_t d = eu < (int64_t)cfl ? eu : (int64_t)cfl;
-                    if (d > 0) {
-                        add_dev(cfa, -(int32_t)d);
-                        add_dev(cf_ptr(g.arc, g.twin[ah]), (int32_t)d);
-                        add_dev(&g.e[u], -d);
-                        add_dev(&g.e[g.arc[ah].x], d);
-                        tl.push++;
-                    }
-                }
-            } else {
-                hu = hh + 1;
-                if (lane == 0) {
-                    g.h[u] = hu;
-                    tl.relabel++;
-                }
-            }
-        }
-    }
+    for (int64_t i = gwave; i < g.n_heavy_all; i += nwaves)
+        rl += discharge_wave<SC>(g, g.heavy_all[i], kc, rc, tl, to_t);
+    flush_to_t<SC>(g, to_t);
+    flush_relabels<SC>(g.ctrl, rl);
 }
 
 // ---------------------------------------------------------------------------
 // RemoveInvalidEdges (Alg. 3): saturate every residual arc (u, v) with
-// h(u) > h(v) + 1.  Only u lowers c_f of its own arcs, so an exchange with 0
+// h(u) > h(v) + 1.  Heights never drop inside a phase and start exact, so only
+// vertices that relabelled in the phase can own such an arc; the phase keeps
+// them in a list.  Only u lowers c_f of its own arcs, so an exchange with 0
 // reads and clears the residual in one step.
 // ---------------------------------------------------------------------------
 
+template <int SC>
 __device__ __forceinline__ void rie_arc(const DevGraph &g, int u, int hu, int a, Tally &tl) {
     const int2 r = g.arc[a];
     if (r.y > 0 && hu > g.h[r.x] + 1) {
-        const int32_t c = xchg_dev(cf_ptr(g.arc, a), 0);
+        const int32_t c = xchg<SC>(cf_ptr(g.arc, a), 0);
         if (c > 0) {
-            add_dev(cf_ptr(g.arc, g.twin[a]), c);
-            add_dev(&g.e[u], -(int64_t)c);
-            add_dev(&g.e[r.x], (int64_t)c);
+            add<SC>(cf_ptr(g.arc, g.twin[a]), c);
+            add<SC>(&g.e[u], -(int64_t)c);
+            add<SC>(&g.e[r.x], (int64_t)c);
             tl.rie_sat++;
         }
     }
 }
 
-__device__ void remove_invalid_lanes(const DevGraph &g, const int32_t *list, int64_t count,
-                                     bool topology, Tally &tl) {
+template <int SC>
+__device__ void remove_invalid(const DevGraph &g, const int32_t *list, int64_t count, Tally &tl) {
     const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = gtid; i < count; i += stride) {
-        const int u = topology ? (int)i : list[i];
-        const int beg = g.row_ptr[u], end = g.row_ptr[u + 1];
-        if (topology && end - beg > kLightMaxDeg) continue;
-        const int hu = g.h[u];
-        for (int a = beg; a < end; ++a) rie_arc(g, u, hu, a, tl);
-        tl.rie_a += end - beg;
-    }
-}
-
-__device__ void remove_invalid_waves(const DevGraph &g, const int32_t *list, int64_t count, Tally &tl) {
+    const int64_t cr = (count + 63) & ~63ll;
     const int lane = lane_id();
-    const int64_t wpb = blockDim.x >> 6;
-    const int64_t gwave = (int64_t)blockIdx.x * wpb + (threadIdx.x >> 6);
-    const int64_t nwaves = (int64_t)gridDim.x * wpb;
-    for (int64_t i = gwave; i < count; i += nwaves) {
-        const int u = list[i];
-        const int beg = g.row_ptr[u], end = g.row_ptr[u + 1];
-        const int hu = g.h[u];
-        for (int a = beg + lane; a < end; a += 64) rie_arc(g, u, hu, a, tl);
-        if (lane == 0) tl.rie_a += end - beg;
+    for (int64_t i = gtid; i < cr; i += stride) {
+        int u = -1, beg = 0, end = 0;
+        bool heavy = false;
+        if (i < count) {
+            u = list[i];
+            beg = g.row_ptr[u];
+            end = g.row_ptr[u + 1];
+            heavy = end - beg > kLightMaxDeg;
+            if (!heavy) {
+                const int hu = g.h[u];
+                for (int a = beg; a < end; ++a) rie_arc<SC>(g, u, hu, a, tl);
+                tl.rie_a += end - beg;
+            }
+        }
+        uint64_t hm = __ballot(heavy);
+        while (hm) {
+            const int l = __ffsll((unsigned long long)hm) - 1;
+            hm &= hm - 1;
+            const int w = __shfl(u, l, 64);
+            const int wb = __shfl(beg, l, 64), we = __shfl(end, l, 64);
+            const int hw = g.h[w];
+            for (int a = wb + lane; a < we; a += 64) rie_arc<SC>(g, w, hw, a, tl);
+            if (lane == 0) tl.rie_a += we - wb;
+        }
     }
 }
 
@@ -468,10 +611,10 @@ __device__ void remove_invalid_waves(const DevGraph &g, const int32_t *list, int
 // The persistent solve loop (Alg. 1 / Alg. 4 while-loop)
 // ---------------------------------------------------------------------------
 
-template <int BLOCK>
+template <int BLOCK, int SC>
 __global__ void __launch_bounds__(BLOCK) k_loop(DevGraph g, LoopParams p) {
     Ctrl *c = g.ctrl;
-    if (ld_dev(&c->err)) return;  // update batch rejected: leave the state alone
+    if (ld<SC>(&c->err)) return;  // update batch rejected: leave the state alone
     Tally tl;
     const bool leader = blockIdx.x == 0 && threadIdx.x == 0;
     const bool topology = p.mode == 1;
@@ -480,63 +623,79 @@ __global__ void __launch_bounds__(BLOCK) k_loop(DevGraph g, LoopParams p) {
     for (;;) {
         // time budget: the leader raised `stop` before the last barrier, so
         // every workgroup sees the same value here
-        if (ld_dev(&c->stop)) {
+        if (ld<SC>(&c->stop)) {
             if (leader) c->status = kDeadline;
             break;
         }
         // --- global relabel ---
         if (leader) {
-            c->nlight = 0;
-            c->nheavy = 0;
-            add_dev(&c->stat[kStGlobalRelabels], 1);
+            for (int k = 0; k < 3; ++k) c->lst[k] = ListCtr{0, 0, 0, 0};
+            c->nrelab = 0;
+            c->phase_relabels = 0;
+            add<SC>(&c->stat[kStGlobalRelabels], 1);
         }
-        bfs_roots(g, tl);
+        const uint64_t tb = wall_clock64();
+        bfs_roots<SC>(g, tl);
         if (!grid_barrier(c, p.barrier_ticks)) return;
         int L = 0;
         for (;;) {
-            const int cnt = ld_dev(&c->qcount[L % 3]);
+            const int cnt = ld<SC>(&c->qcount[L % 3]);
             if (cnt == 0) break;
             if (leader) c->qcount[(L + 2) % 3] = 0;
-            bfs_level(g, L, tl);
+            bfs_level<SC>(g, L, tl);
             if (!grid_barrier(c, p.barrier_ticks)) return;
             ++L;
         }
-        if (leader) add_dev(&c->stat[kStLevels], (int64_t)L);
+        const uint64_t tp = wall_clock64();
+        if (leader) {
+            add<SC>(&c->stat[kStLevels], (int64_t)L);
+            add<SC>(&c->stat[kStBfsTicks], (int64_t)(tp - tb));
+        }
         // --- termination test right after a fresh global relabel ---
-        const int nl = ld_dev(&c->nlight);
-        const int nh = ld_dev(&c->nheavy);
-        if (nl + nh == 0) {
-            if (leader) c->status = kSolved;
-            break;
+        {
+            const int nl = ld<SC>(&c->lst[0].light);
+            const int nh = ld<SC>(&c->lst[0].heavy);
+            if (nl + nh == 0) {
+                if (leader) c->status = kSolved;
+                break;
+            }
         }
         if (p.max_iter >= 0 && iter >= p.max_iter) {
             if (leader) c->status = kIterLimit;
             break;
         }
-        // --- PushRelabel ---
-        if (topology) {
-            push_relabel_lanes(g, nullptr, g.n, true, p.kc, tl);
-            push_relabel_waves(g, g.heavy_all, g.n_heavy_all, p.kc, tl);
-        } else {
-            push_relabel_lanes(g, g.wl_light, nl, false, p.kc, tl);
-            push_relabel_waves(g, g.wl_heavy, nh, p.kc, tl);
+        // --- push/relabel rounds ---
+        const int32_t rbase = p.seq_base + ld<SC>(&c->rounds);
+        const int round_cap = p.rounds_per_level > 0 ? min(p.max_rounds, p.rounds_per_level * L + 16)
+                                                     : p.max_rounds;
+        int r = 0;
+        for (;; ++r) {
+            const int rd = r % 3, wr = (r + 1) % 3, rs = (r + 2) % 3;
+            const int nl = ld<SC>(&c->lst[rd].light);
+            const int nh = ld<SC>(&c->lst[rd].heavy);
+            if (nl + nh == 0) break;
+            if (r >= round_cap || ld<SC>(&c->phase_relabels) > p.relabel_budget) break;
+            if (leader) c->lst[rs] = ListCtr{0, 0, 0, 0};
+            const RoundCtx rc{g.list[wr], &c->lst[wr], rbase + r + 1, rbase};
+            if (topology) pr_round_topology<SC>(g, p.kc, rc, tl);
+            else pr_round<SC>(g, rd, nl, nh, p.kc, rc, tl);
+            if (!grid_barrier(c, p.barrier_ticks)) return;
         }
-        if (!grid_barrier(c, p.barrier_ticks)) return;
-        // --- RemoveInvalidEdges ---
-        if (topology) {
-            remove_invalid_lanes(g, nullptr, g.n, true, tl);
-            remove_invalid_waves(g, g.heavy_all, g.n_heavy_all, tl);
-        } else {
-            remove_invalid_lanes(g, g.wl_light, nl, false, tl);
-            remove_invalid_waves(g, g.wl_heavy, nh, tl);
-        }
+        // --- RemoveInvalidEdges over the vertices that relabelled ---
+        const uint64_t tr = wall_clock64();
+        remove_invalid<SC>(g, g.relab, ld<SC>(&c->nrelab), tl);
         if (leader) {
+            add<SC>(&c->stat[kStPrTicks], (int64_t)(tr - tp));
+            add<SC>(&c->stat[kStRieTicks], (int64_t)(wall_clock64() - tr));
             c->qcount[0] = 0;
             c->qcount[1] = 0;
             c->qcount[2] = 0;
-            add_dev(&c->stat[kStIterations], 1);
+            c->rounds += r + 1;
+            add<SC>(&c->stat[kStIterations], 1);
+            add<SC>(&c->stat[kStRounds], (int64_t)r);
             if ((int64_t)(wall_clock64() - t0) > p.deadline_ticks) c->stop = 1;
         }
+        flush_tally<SC>(c, tl);
         if (!grid_barrier(c, p.barrier_ticks)) return;
         ++iter;
     }
@@ -555,10 +714,10 @@ __global__ void __launch_bounds__(BLOCK) k_loop(DevGraph g, LoopParams p) {
         part = wave_sum(part);
         if (lane_id() == 0 && part) atomicAdd((unsigned long long *)&s_def, (unsigned long long)part);
         __syncthreads();
-        if (threadIdx.x == 0 && s_def) add_dev(&c->deficit, s_def);
+        if (threadIdx.x == 0 && s_def) add<SC>(&c->deficit, s_def);
         if (leader) c->e_t = g.e[g.t];
     }
-    flush_tally<BLOCK>(c, tl);
+    flush_tally<SC>(c, tl);
 }
 
 // ---------------------------------------------------------------------------
@@ -586,7 +745,7 @@ __global__ void k_init_state(DevGraph g) {
 // e(u) += d, e(s) -= d (Alg. 1 third loop; Alg. 4 lines 3-8, where the
 // remaining residual is pushed rather than e(u) overwritten).
 __global__ void k_saturate_source(DevGraph g) {
-    if (ld_dev(&g.ctrl->err)) return;
+    if (ld<kAgent>(&g.ctrl->err)) return;
     __shared__ int64_t s_sum, s_cnt;
     if (threadIdx.x == 0) {
         s_sum = 0;
@@ -600,8 +759,8 @@ __global__ void k_saturate_source(DevGraph g) {
         const int2 r = g.arc[a];
         if (r.y > 0) {
             g.arc[a].y = 0;
-            add_dev(cf_ptr(g.arc, g.twin[a]), r.y);
-            add_dev(&g.e[r.x], (int64_t)r.y);
+            add<kAgent>(cf_ptr(g.arc, g.twin[a]), r.y);
+            add<kAgent>(&g.e[r.x], (int64_t)r.y);
             sum += r.y;
             cnt++;
         }
@@ -614,8 +773,8 @@ __global__ void k_saturate_source(DevGraph g) {
     }
     __syncthreads();
     if (threadIdx.x == 0 && s_sum) {
-        add_dev(&g.e[g.s], -s_sum);
-        add_dev(&g.ctrl->stat[kStSourcePushes], s_cnt);
+        add<kAgent>(&g.e[g.s], -s_sum);
+        add<kAgent>(&g.ctrl->stat[kStSourcePushes], s_cnt);
     }
 }
 
@@ -638,7 +797,7 @@ __global__ void k_validate_updates(DevGraph g, const int64_t *ids, const int32_t
 
 // Alg. 5 first loop: c_f(u,v) += c' - c; the stored capacities follow.
 __global__ void k_apply_delta(DevGraph g, const int64_t *ids, const int32_t *caps, int64_t k) {
-    if (ld_dev(&g.ctrl->err)) return;
+    if (ld<kAgent>(&g.ctrl->err)) return;
     int64_t cnt = 0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < k;
          i += (int64_t)gridDim.x * blockDim.x) {
@@ -648,13 +807,13 @@ __global__ void k_apply_delta(DevGraph g, const int64_t *ids, const int32_t *cap
         g.ecap[id] = cv;
         const int32_t a = g.edge2arc[id];
         if (a >= 0 && d != 0) {
-            add_dev(&g.cap[a], d);
-            add_dev(cf_ptr(g.arc, a), d);
+            add<kAgent>(&g.cap[a], d);
+            add<kAgent>(cf_ptr(g.arc, a), d);
         }
         cnt++;
     }
     cnt = wave_sum(cnt);
-    if (lane_id() == 0 && cnt) add_dev(&g.ctrl->stat[kStUpdates], cnt);
+    if (lane_id() == 0 && cnt) add<kAgent>(&g.ctrl->stat[kStUpdates], cnt);
 }
 
 // Alg. 5 second loop restricted to the updated arc pairs (only they can have
@@ -664,7 +823,7 @@ __global__ void k_apply_delta(DevGraph g, const int64_t *ids, const int32_t *cap
 // sum to the pair's capacity); a compare-and-swap makes each clamp happen
 // once even when several updates share a pair.
 __global__ void k_clamp(DevGraph g, const int64_t *ids, int64_t k) {
-    if (ld_dev(&g.ctrl->err)) return;
+    if (ld<kAgent>(&g.ctrl->err)) return;
     int64_t cnt = 0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < k;
          i += (int64_t)gridDim.x * blockDim.x) {
@@ -675,18 +834,18 @@ __global__ void k_clamp(DevGraph g, const int64_t *ids, int64_t k) {
             const int32_t x = side ? a1 : a0;
             const int32_t y = side ? a0 : a1;
             int32_t *cfx = cf_ptr(g.arc, x);
-            const int32_t cv = ld_dev(cfx);
-            if (cv < 0 && cas_dev(cfx, cv, 0)) {
+            const int32_t cv = ld<kAgent>(cfx);
+            if (cv < 0 && cas<kAgent>(cfx, cv, 0)) {
                 const int32_t o = -cv;
-                add_dev(cf_ptr(g.arc, y), -o);
-                add_dev(&g.e[g.arc[y].x], (int64_t)o);  // tail of x
-                add_dev(&g.e[g.arc[x].x], -(int64_t)o); // head of x
+                add<kAgent>(cf_ptr(g.arc, y), -o);
+                add<kAgent>(&g.e[g.arc[y].x], (int64_t)o);  // tail of x
+                add<kAgent>(&g.e[g.arc[x].x], -(int64_t)o); // head of x
                 cnt++;
             }
         }
     }
     cnt = wave_sum(cnt);
-    if (lane_id() == 0 && cnt) add_dev(&g.ctrl->stat[kStClamps], cnt);
+    if (lane_id() == 0 && cnt) add<kAgent>(&g.ctrl->stat[kStClamps], cnt);
 }
 
 // Certificate: side[v] = 1 when h(v) >= |V|; cut = sum of cap over arcs from
@@ -708,7 +867,7 @@ __global__ void k_min_cut(DevGraph g, uint8_t *side) {
     part = wave_sum(part);
     if (lane_id() == 0 && part) atomicAdd((unsigned long long *)&s_cut, (unsigned long long)part);
     __syncthreads();
-    if (threadIdx.x == 0 && s_cut) add_dev(&g.ctrl->cut, s_cut);
+    if (threadIdx.x == 0 && s_cut) add<kAgent>(&g.ctrl->cut, s_cut);
 }
 
 __global__ void k_fill_i32(int32_t *p, int64_t count, int32_t value) {
@@ -770,7 +929,7 @@ hipError_t launch_clamp(const DevGraph &g, const int64_t *ids, int64_t k, hipStr
 hipError_t loop_max_coresident(int device, int *blocks) {
     int per_cu = 0, cus = 0;
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &per_cu, reinterpret_cast<const void *>(k_loop<kBlock>), kBlock, 0);
+        &per_cu, reinterpret_cast<const void *>(k_loop<kBlock, kAgent>), kBlock, 0);
     if (e != hipSuccess) return e;
     e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
     if (e != hipSuccess) return e;
@@ -780,13 +939,13 @@ hipError_t loop_max_coresident(int device, int *blocks) {
 
 hipError_t launch_loop(const DevGraph &g, const LoopParams &p, int grid, hipStream_t st) {
     if (grid <= 1) {
-        hipLaunchKernelGGL(k_loop<kBlockSingle>, dim3(1), dim3(kBlockSingle), 0, st, g, p);
+        hipLaunchKernelGGL((k_loop<kBlock, kGroup>), dim3(1), dim3(kBlock), 0, st, g, p);
         return hipGetLastError();
     }
     DevGraph ga = g;
     LoopParams pa = p;
     void *args[] = {&ga, &pa};
-    return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_loop<kBlock>), dim3(grid),
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_loop<kBlock, kAgent>), dim3(grid),
                                       dim3(kBlock), args, 0, st);
 }
 

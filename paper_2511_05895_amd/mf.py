@@ -30,15 +30,16 @@ class mf_csr_t(C.Structure):
 class mf_opts_t(C.Structure):
     _fields_ = [("kernel_cycles", C.c_int32), ("mode", C.c_int32), ("grid_blocks", C.c_int32),
                 ("device", C.c_int32), ("max_iterations", C.c_int64), ("time_budget_ms", C.c_int32),
-                ("reserved", C.c_int32 * 7)]
+                ("max_rounds", C.c_int32), ("relabel_budget", C.c_int32), ("rounds_per_level", C.c_int32),
+                ("reserved", C.c_int32 * 4)]
 
 
 class mf_stats_t(C.Structure):
     _fields_ = [(name, C.c_int64) for name in (
         "iterations", "global_relabels", "bfs_levels", "bfs_vertices", "bfs_arcs",
         "pr_vertex_cycles", "pr_arcs", "pushes", "relabels", "rie_arcs", "rie_saturations",
-        "updates", "clamps", "source_pushes", "loop_launches", "grid_blocks")] + [
-        ("loop_kernel_ms", C.c_double), ("call_ms", C.c_double)]
+        "updates", "clamps", "source_pushes", "rounds", "loop_launches", "grid_blocks")] + [
+        (name, C.c_double) for name in ("bfs_ms", "pr_ms", "rie_ms", "loop_kernel_ms", "call_ms")]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -221,9 +222,13 @@ class MaxFlow:
     """Owns one handle.  g: object with n, row_ptr, col, cap, s, t."""
 
     def __init__(self, g, kernel_cycles=0, mode=MF_MODE_DATA, grid_blocks=0, max_iterations=-1,
-                 device=0, cap=None, time_budget_ms=0):
+                 device=0, cap=None, time_budget_ms=0, max_rounds=0, relabel_budget=0,
+                 rounds_per_level=0):
         o = mf_default_opts()
         o.time_budget_ms = time_budget_ms
+        o.max_rounds = max_rounds
+        o.relabel_budget = relabel_budget
+        o.rounds_per_level = rounds_per_level
         o.kernel_cycles = kernel_cycles
         o.mode = mode
         o.grid_blocks = grid_blocks
