@@ -78,8 +78,15 @@ typedef struct {
     int32_t rounds_per_level; /* a phase also ends after this many rounds per
                                level of the BFS that began it (+16); 0 = 2,
                                < 0 = no such cap                             */
-    int32_t reserved[4];    /* must be zero                                   */
+    int32_t flags;          /* MF_FLAG_* bits                                 */
+    int32_t reserved[3];    /* must be zero                                   */
 } mf_opts_t;
+
+/* opts.flags: turn the gap heuristic off (Sec. 2.2 names gap relabelling as a
+ * standard push-relabel heuristic; on by default).  With it, a relabel that
+ * empties a height makes every vertex above it count as cut off from the sink
+ * until the next global relabel. */
+#define MF_FLAG_NO_GAP 1
 
 /* Counters of the last mf_solve / mf_apply_updates* / mf_resume call. */
 typedef struct {
@@ -209,6 +216,16 @@ MF_API int mf_export_graph(mf_handle_t *h, int32_t *row_ptr, int32_t *col, int32
  * int32[m] (current per-edge capacities).  Any pointer may be NULL. */
 MF_API int mf_export_state(mf_handle_t *h, int32_t *cap, int32_t *cf, int64_t *e,
                            int32_t *height, int32_t *ecap);
+
+/* Per-phase trace of the last solving call.  A phase is the work between two
+ * global relabels (Alg. 1/4 loop): one record of 8 int32 per phase, in order,
+ * {BFS levels of the global relabel that opened it, active vertices it found,
+ * push/relabel rounds run, end reason (0 = no active vertex left, 1 = round
+ * cap, 2 = relabel budget), relabels, distinct vertices relabelled, pushes,
+ * 0}.  Copies min(recorded, max_phases) records into out (host,
+ * int32[8 * max_phases]); *n_out receives the number recorded (at most 256).
+ * These are the features of the learned global-relabel schedule. */
+MF_API int mf_get_trace(const mf_handle_t *h, int32_t *out, int32_t max_phases, int32_t *n_out);
 
 /* Run the handle's GPU work on `stream` (a hipStream_t; NULL = the
  * handle's own stream). */

@@ -44,6 +44,7 @@ struct mf_handle {
     int64_t relabel_budget = 0;
     int32_t max_rounds = 0;
     int32_t rounds_per_level = 2;
+    int32_t use_gap = 1;
     double tick_ms = 1e-5;  // one wall-clock tick in ms
     int32_t seq = 1;  // next round id; round ids stamp mark[] and rmark[]
     int32_t epoch = 0;
@@ -145,7 +146,10 @@ int run_loop_and_finish(mf_handle_t *h) {
         h->seq = 1;
     }
     mf::LoopParams p{h->kc, h->mode, h->max_iter, h->deadline_ticks, h->barrier_ticks,
-                     h->relabel_budget, h->max_rounds, h->seq, h->rounds_per_level, 0};
+                     h->relabel_budget, h->max_rounds, h->seq, h->rounds_per_level, h->use_gap};
+    // height counts of the gap heuristic start at zero (the loop clears them
+    // again before every later global relabel)
+    HIP_TRY(h, mf::launch_fill_i32(h->g.hcount, (int64_t)h->g.n + 1, 0, h->stream));
     HIP_TRY(h, hipEventRecord(h->ev[1], h->stream));
     HIP_TRY(h, mf::launch_loop(h->g, p, h->grid, h->stream));
     HIP_TRY(h, hipEventRecord(h->ev[2], h->stream));
@@ -234,7 +238,8 @@ bool opts_valid(const mf_opts_t &o, std::string *why) {
     if (o.time_budget_ms < 0) { *why = "time_budget_ms must be >= 0"; return false; }
     if (o.max_rounds < 0) { *why = "max_rounds must be >= 0"; return false; }
     if (o.relabel_budget < 0) { *why = "relabel_budget must be >= 0"; return false; }
-    for (int i = 0; i < 4; ++i)
+    if (o.flags & ~MF_FLAG_NO_GAP) { *why = "unknown flags"; return false; }
+    for (int i = 0; i < 3; ++i)
         if (o.reserved[i]) { *why = "reserved fields must be zero"; return false; }
     return true;
 }
@@ -307,6 +312,7 @@ MF_API int mf_create(const mf_csr_t *g, const int32_t *cap, int32_t s, int32_t t
     h->max_rounds = o.max_rounds > 0 ? o.max_rounds : 65536;
     h->relabel_budget = o.relabel_budget > 0 ? o.relabel_budget : std::max<int64_t>(1024, n / 2);
     h->rounds_per_level = o.rounds_per_level == 0 ? 2 : (o.rounds_per_level < 0 ? 0 : o.rounds_per_level);
+    h->use_gap = (o.flags & MF_FLAG_NO_GAP) ? 0 : 1;
     h->kc = o.kernel_cycles > 0 ? o.kernel_cycles
                                 : (int32_t)std::max<int64_t>(1, (int64_t)((double)m / n + 0.5));
     auto bail = [&](int code, const std::string &msg) {
@@ -361,7 +367,7 @@ MF_API int mf_create(const mf_csr_t *g, const int32_t *cap, int32_t s, int32_t t
     ALLOC(d.mark, n);
     ALLOC(d.rmark, n);
     ALLOC(d.relab, n);
-    ALLOC(d.cur, n);
+    ALLOC(d.hcount, (int64_t)n + 1);
     ALLOC(d.heavy_all, (int64_t)heavy.size());
     ALLOC(d.ctrl, 1);
     ALLOC(h->d_side, n);
@@ -383,7 +389,7 @@ MF_API int mf_create(const mf_csr_t *g, const int32_t *cap, int32_t s, int32_t t
     if ((e = mf::launch_fill_i32(d.stamp, m, 0, h->stream)) != hipSuccess ||
         (e = mf::launch_fill_i32(d.mark, n, 0, h->stream)) != hipSuccess ||
         (e = mf::launch_fill_i32(d.rmark, n, 0, h->stream)) != hipSuccess ||
-        (e = mf::launch_fill_i32(d.cur, n, 0, h->stream)) != hipSuccess ||
+
         (e = mf::launch_reset_ctrl(d, h->stream)) != hipSuccess ||
         (e = hipStreamSynchronize(h->stream)) != hipSuccess)
         return bail(MF_EDEVICE, std::string("init: ") + hipGetErrorString(e));
@@ -567,6 +573,17 @@ MF_API int mf_export_state(mf_handle_t *h, int32_t *cap, int32_t *cf, int64_t *e
     if (ecap && d.m)
         HIP_TRY(h, hipMemcpyAsync(ecap, d.ecap, sizeof(int32_t) * d.m, hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(h, hipStreamSynchronize(h->stream));
+    return MF_OK;
+}
+
+MF_API int mf_get_trace(const mf_handle_t *h, int32_t *out, int32_t max_phases, int32_t *n_out) {
+    if (!h || (max_phases > 0 && !out) || max_phases < 0)
+        return fail(const_cast<mf_handle_t *>(h), MF_EINVAL, "bad trace arguments");
+    const mf::Ctrl &c = *h->h_ctrl;
+    const int32_t nrec = std::min<int32_t>(c.ntrace, mf::kTraceCap);
+    const int32_t k = std::min(nrec, max_phases);
+    if (k > 0) std::memcpy(out, c.trace, sizeof(int32_t) * mf::kTraceFields * k);
+    if (n_out) *n_out = nrec;
     return MF_OK;
 }
 

@@ -16,6 +16,21 @@ constexpr int kChunk = 256;
 // Threads per workgroup of the persistent solve kernel.
 constexpr int kBlock = 1024;
 
+// Per-phase trace records kept by the persistent kernel (one per global
+// relabel that found active vertices): the first kTraceCap of a call.
+constexpr int kTraceCap = 256;
+constexpr int kTraceFields = 8;
+enum : int {
+    kTrLevels = 0,   // BFS levels of the global relabel that opened the phase
+    kTrActive,       // active vertices it found
+    kTrRounds,       // push/relabel rounds run
+    kTrReason,       // why the phase ended: 0 no active vertex left, 1 round cap, 2 relabel budget
+    kTrRelabels,     // relabels in the phase
+    kTrRelabelled,   // distinct vertices relabelled
+    kTrPushes,       // pushes in the phase
+    kTrSpare
+};
+
 // Loop status written by the persistent kernel.
 enum : int32_t { kRunning = 0, kSolved = 1, kIterLimit = 2, kAborted = 3, kDeadline = 4 };
 
@@ -72,6 +87,10 @@ struct Ctrl {
     int32_t rounds;     // push/relabel rounds run by this call (round ids)
     int32_t pad_;
     int64_t phase_relabels;  // relabels of the current phase
+    int64_t phase_pushes;    // pushes of the current phase
+    int32_t ntrace;          // phases recorded in trace[]
+    int32_t gap;             // lowest height found empty in this phase (|V| = none)
+    int32_t trace[kTraceCap][kTraceFields];
     int64_t deficit;    // sum of e(v) < 0 over v not in {s, t} at termination
     int64_t e_t;        // e(t) at termination
     int64_t cut;        // cut capacity (k_min_cut)
@@ -98,7 +117,7 @@ struct DevGraph {
     int32_t *mark;      // n: id of the round list a vertex was last added to
     int32_t *rmark;     // n: id of the phase a vertex last relabelled in
     int32_t *relab;     // n: vertices relabelled in the current phase
-    int32_t *cur;       // n: current arc of each vertex (offset in its list)
+    int32_t *hcount;    // n+1: vertices at each height below |V| (gap heuristic)
     int32_t *heavy_all; // vertices with long arc lists (topology-driven sweeps)
     int32_t n_heavy_all;
     Ctrl *ctrl;
@@ -115,7 +134,7 @@ struct LoopParams {
     int32_t seq_base;        // first round id of this call (marks stay unique)
     int32_t rounds_per_level;  // > 0: a phase also stops after this many rounds per
                                // level of the BFS that started it (+16)
-    int32_t pad_;
+    int32_t use_gap;           // gap heuristic on (1) or off (0)
 };
 
 // ---- launch wrappers (mf_kernels.hip) ----

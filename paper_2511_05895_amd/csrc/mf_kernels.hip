@@ -223,18 +223,21 @@ __device__ void bfs_roots(const DevGraph &g, Tally &tl) {
     for (int64_t i = gtid; i < nr; i += stride) {
         const int v = (int)i;
         bool root = false;
-        int deg = 0, beg = 0;
+        int beg = 0, end = 0;
         if (i < g.n) {
             root = (v == g.t) || (v != g.s && g.e[v] < 0);
             g.h[v] = root ? 0 : g.n;
             if (root) {
                 beg = g.row_ptr[v];
-                deg = g.row_ptr[v + 1] - beg;
+                end = g.row_ptr[v + 1];
             }
         }
-        const int c = root ? n_items(deg) : 0;
+        const int c = root ? n_items(end - beg) : 0;
+        const int nroot = (int)wave_sum((int64_t)root);
+        if (lane_id() == 0 && nroot) add<SC>(&g.hcount[0], nroot);
         const int base = wave_appendn<SC>(&g.ctrl->qcount[0], c);
-        for (int j = 0; j < c; ++j) g.q[0][base + j] = make_int2(v, beg + j * kChunk);
+        for (int j = 0; j < c; ++j)
+            g.q[0][base + j] = make_int2(beg + j * kChunk, min(beg + (j + 1) * kChunk, end));
         tl.bfs_v += root;
     }
 }
@@ -259,10 +262,9 @@ __device__ void bfs_level(const DevGraph &g, int L, Tally &tl) {
         const int64_t idx = base + lane;
         int beg = 0, len = 0;
         if (idx < cnt) {
-            const int2 it = qin[idx];
-            beg = it.y;
-            const int end = min(beg + kChunk, g.row_ptr[it.x + 1]);
-            len = end - beg;
+            const int2 it = qin[idx];  // arc range {first, end} of one item
+            beg = it.x;
+            len = it.y - it.x;
         }
         const int incl = wave_incl_scan(len);
         const int excl = incl - len;
@@ -283,24 +285,31 @@ __device__ void bfs_level(const DevGraph &g, int L, Tally &tl) {
             int v = -1;
             if (j < total) {
                 const int a = obeg + (j - oexcl);
-                v = g.arc[a].x;
+                // the head and the twin index come in one step, the head's height
+                // and the twin's residual in the next
+                const int2 rec = g.arc[a];
+                const int tw = g.twin[a];
+                v = rec.x;
+                const int hv = g.h[v];
+                const int cft = g.arc[tw].y;
                 tl.bfs_a++;
-                if (v != g.s && g.h[v] == n) {
-                    const int tw = g.twin[a];
-                    if (g.arc[tw].y > 0) disc = cas<SC>(&g.h[v], n, L + 1);
-                }
+                if (v != g.s && hv == n && cft > 0) disc = cas<SC>(&g.h[v], n, L + 1);
             }
-            int vbeg = 0, vdeg = 0;
+            int vbeg = 0, vend = 0;
             bool active = false;
             if (disc) {
                 vbeg = g.row_ptr[v];
-                vdeg = g.row_ptr[v + 1] - vbeg;
+                vend = g.row_ptr[v + 1];
                 active = (v != g.t) && g.e[v] > 0;
                 tl.bfs_v++;
             }
+            const int vdeg = vend - vbeg;
+            const int ndisc = __popcll(__ballot(disc));
+            if (lane_id() == 0 && ndisc) add<SC>(&g.hcount[L + 1], ndisc);
             const int c = disc ? n_items(vdeg) : 0;
             const int qb = wave_appendn<SC>(qout_count, c);
-            for (int k = 0; k < c; ++k) qout[qb + k] = make_int2(v, vbeg + k * kChunk);
+            for (int k = 0; k < c; ++k)
+                qout[qb + k] = make_int2(vbeg + k * kChunk, min(vbeg + (k + 1) * kChunk, vend));
             const bool light = active && vdeg <= kLightMaxDeg;
             const bool heavy = active && vdeg > kLightMaxDeg;
             const int sl = wave_append1<SC>(&g.ctrl->lst[0].light, light);
@@ -334,6 +343,7 @@ struct RoundCtx {
     ListCtr *next_ctr;
     int32_t next_id;   // round id stamped into mark[] for that list
     int32_t phase_id;  // stamped into rmark[] on a vertex's first relabel
+    bool use_gap;      // gap heuristic on
 };
 
 // Add v to the next round's list unless it is already there.
@@ -361,6 +371,28 @@ __device__ __forceinline__ void note_relabel(const DevGraph &g, int u, int32_t p
     }
 }
 
+// Relabel u from height ho to hmin + 1 (Alg. 2), keeping the per-height
+// counts of the gap heuristic: a height left empty by this move means every
+// vertex above it has no residual path to a root under a valid labelling
+// (heights drop by at most one per residual arc), so heights above the lowest
+// such gap count as |V|.  A count that hits zero only transiently (racing
+// relabels) just deactivates vertices that the next global relabel restores.
+// Returns the new height.
+template <int SC>
+__device__ __forceinline__ int relabel_to(const DevGraph &g, int u, int ho, int hmin, bool use_gap) {
+    int hn = hmin + 1;
+    if (use_gap) {
+        const int gap = ld<SC>(&g.ctrl->gap);
+        if (hn > gap) hn = g.n;
+        if (hn < g.n) add<SC>(&g.hcount[hn], 1);
+        if (fetch_add<SC>(&g.hcount[ho], -1) == 1 && ho > 0)
+            __hip_atomic_fetch_min(&g.ctrl->gap, ho, __ATOMIC_RELAXED, SC);
+    }
+    if (hn > g.n) hn = g.n;
+    g.h[u] = hn;
+    return hn;
+}
+
 // Push d from u along arc a to v = head(a).  Residual capacity moves to the
 // twin; excess moves from u to v except that the excess taken from u is
 // subtracted by the caller (one atomic per visit chunk).
@@ -385,6 +417,11 @@ __device__ int discharge_lane(const DevGraph &g, int u, int kc, const RoundCtx &
     const int beg = g.row_ptr[u], end = g.row_ptr[u + 1];
     int hu = g.h[u];
     int relabels = 0;
+    if (rc.use_gap && hu < n && hu > ld<SC>(&g.ctrl->gap)) {  // above a gap: cut off
+        add<SC>(&g.hcount[hu], -1);
+        hu = n;
+        g.h[u] = n;
+    }
     for (int cyc = 0; cyc < kc && hu < n; ++cyc) {
         int64_t eu = ld<SC>(&g.e[u]);
         if (eu <= 0) break;
@@ -410,8 +447,7 @@ __device__ int discharge_lane(const DevGraph &g, int u, int kc, const RoundCtx &
             }
             if (sent) add<SC>(&g.e[u], -sent);
         } else {
-            hu = hmin + 1;
-            g.h[u] = hu;
+            hu = relabel_to<SC>(g, u, hu, hmin, rc.use_gap);
             tl.relabel++;
             relabels++;
             note_relabel<SC>(g, u, rc.phase_id);
@@ -432,6 +468,13 @@ __device__ int discharge_wave(const DevGraph &g, int u, int kc, const RoundCtx &
     const int beg = g.row_ptr[u], end = g.row_ptr[u + 1];
     int hu = g.h[u];
     int relabels = 0;
+    if (rc.use_gap && hu < n && hu > ld<SC>(&g.ctrl->gap)) {  // above a gap: cut off
+        if (lane == 0) {
+            add<SC>(&g.hcount[hu], -1);
+            g.h[u] = n;
+        }
+        hu = n;
+    }
     for (int cyc = 0; cyc < kc && hu < n; ++cyc) {
         int64_t eu = 0;
         if (lane == 0) eu = ld<SC>(&g.e[u]);
@@ -479,13 +522,14 @@ __device__ int discharge_wave(const DevGraph &g, int u, int kc, const RoundCtx &
             }
             if (lane == 0 && sent) add<SC>(&g.e[u], -sent);
         } else {
-            hu = hmin + 1;
-            relabels++;
+            int hn = 0;
             if (lane == 0) {
-                g.h[u] = hu;
+                hn = relabel_to<SC>(g, u, hu, hmin, rc.use_gap);
                 tl.relabel++;
                 note_relabel<SC>(g, u, rc.phase_id);
             }
+            hu = __shfl(hn, 0, 64);
+            relabels++;
         }
     }
     if (lane == 0 && hu < n && ld<SC>(&g.e[u]) > 0) list_add<SC>(g, rc, u);
@@ -501,9 +545,11 @@ __device__ __forceinline__ void flush_to_t(const DevGraph &g, int64_t &to_t) {
 }
 
 template <int SC>
-__device__ __forceinline__ void flush_relabels(Ctrl *c, int64_t &rl) {
+__device__ __forceinline__ void flush_relabels(Ctrl *c, int64_t &rl, int64_t pushes) {
     const int64_t s = wave_sum(rl);
+    const int64_t p = wave_sum(pushes);
     if (lane_id() == 0 && s) add<SC>(&c->phase_relabels, s);
+    if (lane_id() == 0 && p) add<SC>(&c->phase_pushes, p);
     rl = 0;
 }
 
@@ -516,10 +562,11 @@ __device__ void pr_round(const DevGraph &g, int rd, int nl, int nh, int kc, cons
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const int32_t *lst = g.list[rd];
     int64_t to_t = 0, rl = 0;
+    const uint32_t push0 = tl.push;
     for (int64_t i = gtid; i < nl; i += stride) rl += discharge_lane<SC>(g, lst[i], kc, rc, tl, to_t);
     flush_to_t<SC>(g, to_t);
     int32_t *grab = &g.ctrl->lst[rd].grab;
-    for (;;) {
+    for (; nh > 0;) {
         int idx = 0;
         if (lane_id() == 0) idx = fetch_add<SC>(grab, 1);
         idx = __shfl(idx, 0, 64);
@@ -527,7 +574,7 @@ __device__ void pr_round(const DevGraph &g, int rd, int nl, int nh, int kc, cons
         rl += discharge_wave<SC>(g, lst[g.n - 1 - idx], kc, rc, tl, to_t);
     }
     flush_to_t<SC>(g, to_t);
-    flush_relabels<SC>(g.ctrl, rl);
+    flush_relabels<SC>(g.ctrl, rl, (int64_t)(tl.push - push0));
 }
 
 // One topology-driven round: every vertex is visited (idle when inactive).
@@ -536,6 +583,7 @@ __device__ void pr_round_topology(const DevGraph &g, int kc, const RoundCtx &rc,
     const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     int64_t to_t = 0, rl = 0;
+    const uint32_t push0 = tl.push;
     for (int64_t i = gtid; i < g.n; i += stride) {
         const int u = (int)i;
         if (u == g.s || u == g.t) continue;
@@ -549,7 +597,7 @@ __device__ void pr_round_topology(const DevGraph &g, int kc, const RoundCtx &rc,
     for (int64_t i = gwave; i < g.n_heavy_all; i += nwaves)
         rl += discharge_wave<SC>(g, g.heavy_all[i], kc, rc, tl, to_t);
     flush_to_t<SC>(g, to_t);
-    flush_relabels<SC>(g.ctrl, rl);
+    flush_relabels<SC>(g.ctrl, rl, (int64_t)(tl.push - push0));
 }
 
 // ---------------------------------------------------------------------------
@@ -574,8 +622,13 @@ __device__ __forceinline__ void rie_arc(const DevGraph &g, int u, int hu, int a,
     }
 }
 
+// With the gap heuristic on, a vertex cut off at height |V| is skipped: its arcs
+// look steep only because it was lifted deliberately, and saturating them
+// would push flow out of the source side and create deficits (new roots)
+// there, undoing the cut.
 template <int SC>
-__device__ void remove_invalid(const DevGraph &g, const int32_t *list, int64_t count, Tally &tl) {
+__device__ void remove_invalid(const DevGraph &g, const int32_t *list, int64_t count, bool skip_cut,
+                               Tally &tl) {
     const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const int64_t cr = (count + 63) & ~63ll;
@@ -585,13 +638,17 @@ __device__ void remove_invalid(const DevGraph &g, const int32_t *list, int64_t c
         bool heavy = false;
         if (i < count) {
             u = list[i];
-            beg = g.row_ptr[u];
-            end = g.row_ptr[u + 1];
-            heavy = end - beg > kLightMaxDeg;
-            if (!heavy) {
-                const int hu = g.h[u];
-                for (int a = beg; a < end; ++a) rie_arc<SC>(g, u, hu, a, tl);
-                tl.rie_a += end - beg;
+            const int hu = g.h[u];
+            if (skip_cut && hu >= g.n) {
+                u = -1;
+            } else {
+                beg = g.row_ptr[u];
+                end = g.row_ptr[u + 1];
+                heavy = end - beg > kLightMaxDeg;
+                if (!heavy) {
+                    for (int a = beg; a < end; ++a) rie_arc<SC>(g, u, hu, a, tl);
+                    tl.rie_a += end - beg;
+                }
             }
         }
         uint64_t hm = __ballot(heavy);
@@ -632,6 +689,8 @@ __global__ void __launch_bounds__(BLOCK) k_loop(DevGraph g, LoopParams p) {
             for (int k = 0; k < 3; ++k) c->lst[k] = ListCtr{0, 0, 0, 0};
             c->nrelab = 0;
             c->phase_relabels = 0;
+            c->phase_pushes = 0;
+            c->gap = g.n;
             add<SC>(&c->stat[kStGlobalRelabels], 1);
         }
         const uint64_t tb = wall_clock64();
@@ -668,22 +727,48 @@ __global__ void __launch_bounds__(BLOCK) k_loop(DevGraph g, LoopParams p) {
         const int32_t rbase = p.seq_base + ld<SC>(&c->rounds);
         const int round_cap = p.rounds_per_level > 0 ? min(p.max_rounds, p.rounds_per_level * L + 16)
                                                      : p.max_rounds;
-        int r = 0;
+        const int active0 = ld<SC>(&c->lst[0].light) + ld<SC>(&c->lst[0].heavy);
+        int r = 0, reason = 0;
         for (;; ++r) {
             const int rd = r % 3, wr = (r + 1) % 3, rs = (r + 2) % 3;
             const int nl = ld<SC>(&c->lst[rd].light);
             const int nh = ld<SC>(&c->lst[rd].heavy);
             if (nl + nh == 0) break;
-            if (r >= round_cap || ld<SC>(&c->phase_relabels) > p.relabel_budget) break;
+            if (r >= round_cap) {
+                reason = 1;
+                break;
+            }
+            if (ld<SC>(&c->phase_relabels) > p.relabel_budget) {
+                reason = 2;
+                break;
+            }
             if (leader) c->lst[rs] = ListCtr{0, 0, 0, 0};
-            const RoundCtx rc{g.list[wr], &c->lst[wr], rbase + r + 1, rbase};
+            const RoundCtx rc{g.list[wr], &c->lst[wr], rbase + r + 1, rbase, p.use_gap != 0};
             if (topology) pr_round_topology<SC>(g, p.kc, rc, tl);
             else pr_round<SC>(g, rd, nl, nh, p.kc, rc, tl);
             if (!grid_barrier(c, p.barrier_ticks)) return;
         }
         // --- RemoveInvalidEdges over the vertices that relabelled ---
         const uint64_t tr = wall_clock64();
-        remove_invalid<SC>(g, g.relab, ld<SC>(&c->nrelab), tl);
+        const int nrel = ld<SC>(&c->nrelab);
+        remove_invalid<SC>(g, g.relab, nrel, p.use_gap != 0, tl);
+        for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= g.n;
+             i += (int64_t)gridDim.x * blockDim.x)
+            g.hcount[i] = 0;
+        {
+            if (leader && c->ntrace < kTraceCap) {
+                int32_t *tr_rec = c->trace[c->ntrace];
+                tr_rec[kTrLevels] = L;
+                tr_rec[kTrActive] = active0;
+                tr_rec[kTrRounds] = r;
+                tr_rec[kTrReason] = reason;
+                tr_rec[kTrRelabels] = (int32_t)min<int64_t>(ld<SC>(&c->phase_relabels), INT32_MAX);
+                tr_rec[kTrRelabelled] = nrel;
+                tr_rec[kTrPushes] = (int32_t)min<int64_t>(ld<SC>(&c->phase_pushes), INT32_MAX);
+                tr_rec[kTrSpare] = 0;
+                c->ntrace++;
+            }
+        }
         if (leader) {
             add<SC>(&c->stat[kStPrTicks], (int64_t)(tr - tp));
             add<SC>(&c->stat[kStRieTicks], (int64_t)(wall_clock64() - tr));

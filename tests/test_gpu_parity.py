@@ -304,3 +304,20 @@ def test_repeat_runs_identical_value_and_cut(mf):
         with mf.MaxFlow(g, grid_blocks=[0, 4, 32, 1][rep]) as F:
             assert F.solve() == value
             assert np.array_equal(F.min_cut()[0], side)
+
+
+@pytest.mark.parametrize("flags", [0, 1])
+@pytest.mark.parametrize("which", ["grid", "rmat"])
+def test_gap_heuristic_on_and_off(mf, flags, which):
+    """The gap heuristic only changes the schedule: values, cuts and the
+    validated state are the same with it on (default) and off."""
+    g = W.seg_grid(96, seed=4) if which == "grid" else W.rmat(14, 16, seed=6)
+    inc = 100 if which == "grid" else 1000
+    with mf.MaxFlow(g, flags=flags) as F:
+        F.solve()
+        check_solved(F, g, g.cap)
+        cap = g.cap.copy()
+        for ids, new in W.batch_chain(g, 0.01, 3, inc, seed=W.SEED_BASE + 11):
+            cap[ids] = new
+            F.update(ids, new)
+            check_solved(F, g, cap)

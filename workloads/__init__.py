@@ -229,3 +229,39 @@ def apply_batch(cap: np.ndarray, ids: np.ndarray, new: np.ndarray) -> np.ndarray
     out = cap.copy()
     out[ids] = new
     return out
+
+
+# --------------------------------------------------------------------------
+# Many independent instances (batched solve)
+# --------------------------------------------------------------------------
+
+def grid_instance(side: int, seed, cap_lo: int = 1, cap_hi: int = 1000) -> Graph:
+    """side x side 4-connected grid, both directions of every neighbour pair,
+    plus s->p and p->t for every pixel; all capacities U[cap_lo, cap_hi].
+    Pixels row-major, s = side^2, t = side^2 + 1."""
+    rng = rng_for(seed, 0)
+    npx = side * side
+    s, t = npx, npx + 1
+    idx = np.arange(npx, dtype=np.int64).reshape(side, side)
+    pa = np.concatenate([idx[:, :-1].ravel(), idx[:-1, :].ravel()])
+    pb = np.concatenate([idx[:, 1:].ravel(), idx[1:, :].ravel()])
+    src = np.concatenate([pa, pb, np.full(npx, s, np.int64), np.arange(npx, dtype=np.int64)])
+    dst = np.concatenate([pb, pa, np.arange(npx, dtype=np.int64), np.full(npx, t, np.int64)])
+    cap = rng.integers(cap_lo, cap_hi + 1, src.shape[0], dtype=np.int64)
+    return edges_to_csr(npx + 2, src, dst, cap, s, t)
+
+
+def c4_instances(count: int = 256, seed=SEED_BASE + 3):
+    """Uneven batch: even i -> grid of side round(32 * 8^u), u ~ U[0,1]
+    (32..256); odd i -> random graph with round(1000 * 50^u) vertices
+    (1k..50k), 8 edges per vertex, s = 0, t = n-1; capacities U[1,1000]."""
+    rng = rng_for(seed, 0)
+    out = []
+    for i in range(count):
+        u = float(rng.random())
+        if i % 2 == 0:
+            out.append(grid_instance(int(round(32 * 8 ** u)), int(seed) * 1000 + i))
+        else:
+            n = int(round(1000 * 50 ** u))
+            out.append(random_graph(n, 8 * n, 1, 1000, int(seed) * 1000 + i, s=0, t=n - 1))
+    return out
