@@ -138,9 +138,67 @@ def summarize_profile(path):
               f"{min(v) / 1e6:.4f} | {max(v) / 1e6:.4f} | {100.0 * sum(v) / total:.2f} |")
 
 
+def _pmc_rows(db, counter):
+    """(kernel name, dispatch id, value) of one counter from a rocprofv3 rocpd database."""
+    import sqlite3
+    cur = sqlite3.connect(db).cursor()
+    q = ("select kernel_name, dispatch_id, value from counters_collection "
+         "where counter_name = ? order by dispatch_id")
+    return list(cur.execute(q, (counter,)))
+
+
+def summarize_pmc(fetch_db, write_db, config, calib_mib, skip_first, command):
+    """HBM traffic of the persistent solve loop from two rocprofv3 --pmc runs
+    (FETCH_SIZE, then WRITE_SIZE; both in KiB per dispatch).  Each counter is
+    scaled by what it reads for the calibration kernel of the same process, an
+    elementwise float32 negate over calib_mib MiB (reads and writes exactly
+    that many bytes).  The first `skip_first` loop launches (the initial
+    from-scratch solves, outside the timed steps) are left out.  Writes
+    profiles/k_loop_<config>_pmc.json and prints a Markdown summary."""
+    known = calib_mib * 1024.0  # KiB moved by one calibration dispatch
+    out = {"kernel_digest": kernel_source_digest(), "command": command,
+           "calibration": f"float32 negate over {calib_mib} MiB (torch.neg), {known:.0f} KiB read and written"}
+    lines = [f"# HBM traffic of k_loop, {CONFIGS[config]['desc']}", "", "Command:", "", "```", command, "```", "",
+             "| counter | calibration KiB/dispatch (known) | factor | k_loop launches | k_loop KiB/launch (raw) | "
+             "k_loop bytes/launch (scaled) |", "|---|---|---|---|---|---|"]
+    total = 0.0
+    for key, db, counter in (("fetch", fetch_db, "FETCH_SIZE"), ("write", write_db, "WRITE_SIZE")):
+        rows = _pmc_rows(db, counter)
+        cal = [v for name, _, v in rows if "neg" in name and "elementwise" in name]
+        loop = [v for name, _, v in rows if "k_loop" in name][skip_first:]
+        if not cal or not loop:
+            raise SystemExit(f"{db}: no calibration ({len(cal)}) or k_loop ({len(loop)}) dispatches for {counter}")
+        cal_kib = float(np.median(cal))
+        factor = known / cal_kib
+        per = float(np.mean(loop)) * 1024.0 * factor
+        total += per
+        out[f"{key}_bytes_per_launch"] = per
+        out[f"{key}_factor"] = factor
+        out[f"{key}_launches"] = len(loop)
+        lines.append(f"| {counter} | {cal_kib:.0f} ({known:.0f}) | {factor:.4f} | {len(loop)} | "
+                     f"{np.mean(loop):.0f} | {per:.4g} |")
+    out["bytes_per_launch"] = total
+    lines += ["", f"HBM bytes per k_loop launch (fetch + write, scaled): {total:.4g}"]
+    path = os.path.join(ROOT, "profiles", f"k_loop_{config}_pmc.json")
+    with open(path, "w") as f:
+        json.dump(out, f, indent=1)
+    print("\n".join(lines))
+
+
 def main():
     if len(sys.argv) == 3 and sys.argv[1] == "--summarize-profile":
         summarize_profile(sys.argv[2])
+        return
+    if len(sys.argv) > 1 and sys.argv[1] == "--summarize-pmc":
+        sp = argparse.ArgumentParser()
+        sp.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DB", "WRITE_DB"))
+        sp.add_argument("--config", default="grid512", choices=sorted(CONFIGS))
+        sp.add_argument("--calibration-copy-mib", type=int, default=256)
+        sp.add_argument("--skip-first", type=int, default=2)
+        sp.add_argument("--command", default="")
+        a = sp.parse_args()
+        summarize_pmc(a.summarize_pmc[0], a.summarize_pmc[1], a.config, a.calibration_copy_mib,
+                      a.skip_first, a.command)
         return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -152,6 +210,8 @@ def main():
     ap.add_argument("--grid-blocks", type=int, default=16)
     ap.add_argument("--kernel-cycles", type=int, default=1)
     ap.add_argument("--mode", type=int, default=0)
+    ap.add_argument("--calibration-copy-mib", type=int, default=0,
+                    help="run a float32 negate over this many MiB first (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: the method here is a single-GPU solver "
@@ -164,6 +224,13 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
+    if args.calibration_copy_mib > 0:
+        src = torch.ones(args.calibration_copy_mib << 18, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
     cfg = CONFIGS[args.config]
     g, seed = make_graph(args.config)
     K, Wm = args.steps, args.warmup

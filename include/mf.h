@@ -79,14 +79,20 @@ typedef struct {
                                level of the BFS that began it (+16); 0 = 2,
                                < 0 = no such cap                             */
     int32_t flags;          /* MF_FLAG_* bits                                 */
-    int32_t reserved[3];    /* must be zero                                   */
+    int32_t stall_rounds;   /* a phase also ends once no excess has reached t
+                               or a deficient vertex for max(stall_rounds, L)
+                               rounds, L = levels of the BFS that began it
+                               (exact labels bring excess that only moves
+                               downhill to a root within L rounds);
+                               0 = 3, < 0 = no such rule                     */
+    int32_t reserved[2];    /* must be zero                                   */
 } mf_opts_t;
 
-/* opts.flags: turn the gap heuristic off (Sec. 2.2 names gap relabelling as a
- * standard push-relabel heuristic; on by default).  With it, a relabel that
+/* opts.flags: turn the gap heuristic on (Sec. 2.2 names gap relabelling as a
+ * standard push-relabel heuristic; off by default).  With it, a relabel that
  * empties a height makes every vertex above it count as cut off from the sink
  * until the next global relabel. */
-#define MF_FLAG_NO_GAP 1
+#define MF_FLAG_GAP 1
 
 /* Counters of the last mf_solve / mf_apply_updates* / mf_resume call. */
 typedef struct {
@@ -221,8 +227,9 @@ MF_API int mf_export_state(mf_handle_t *h, int32_t *cap, int32_t *cf, int64_t *e
  * global relabels (Alg. 1/4 loop): one record of 8 int32 per phase, in order,
  * {BFS levels of the global relabel that opened it, active vertices it found,
  * push/relabel rounds run, end reason (0 = no active vertex left, 1 = round
- * cap, 2 = relabel budget), relabels, distinct vertices relabelled, pushes,
- * 0}.  Copies min(recorded, max_phases) records into out (host,
+ * cap, 2 = relabel budget, 3 = rounds without delivery), relabels, distinct
+ * vertices relabelled, pushes, last round in which excess reached t or a
+ * deficient vertex}.  Copies min(recorded, max_phases) records into out (host,
  * int32[8 * max_phases]); *n_out receives the number recorded (at most 256).
  * These are the features of the learned global-relabel schedule. */
 MF_API int mf_get_trace(const mf_handle_t *h, int32_t *out, int32_t max_phases, int32_t *n_out);

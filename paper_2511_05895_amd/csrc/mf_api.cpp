@@ -44,7 +44,8 @@ struct mf_handle {
     int64_t relabel_budget = 0;
     int32_t max_rounds = 0;
     int32_t rounds_per_level = 2;
-    int32_t use_gap = 1;
+    int32_t use_gap = 0;
+    int32_t stall_rounds = 3;
     double tick_ms = 1e-5;  // one wall-clock tick in ms
     int32_t seq = 1;  // next round id; round ids stamp mark[] and rmark[]
     int32_t epoch = 0;
@@ -146,7 +147,8 @@ int run_loop_and_finish(mf_handle_t *h) {
         h->seq = 1;
     }
     mf::LoopParams p{h->kc, h->mode, h->max_iter, h->deadline_ticks, h->barrier_ticks,
-                     h->relabel_budget, h->max_rounds, h->seq, h->rounds_per_level, h->use_gap};
+                     h->relabel_budget, h->max_rounds, h->seq, h->rounds_per_level, h->use_gap,
+                     h->stall_rounds, 0};
     // height counts of the gap heuristic start at zero (the loop clears them
     // again before every later global relabel)
     HIP_TRY(h, mf::launch_fill_i32(h->g.hcount, (int64_t)h->g.n + 1, 0, h->stream));
@@ -238,8 +240,8 @@ bool opts_valid(const mf_opts_t &o, std::string *why) {
     if (o.time_budget_ms < 0) { *why = "time_budget_ms must be >= 0"; return false; }
     if (o.max_rounds < 0) { *why = "max_rounds must be >= 0"; return false; }
     if (o.relabel_budget < 0) { *why = "relabel_budget must be >= 0"; return false; }
-    if (o.flags & ~MF_FLAG_NO_GAP) { *why = "unknown flags"; return false; }
-    for (int i = 0; i < 3; ++i)
+    if (o.flags & ~MF_FLAG_GAP) { *why = "unknown flags"; return false; }
+    for (int i = 0; i < 2; ++i)
         if (o.reserved[i]) { *why = "reserved fields must be zero"; return false; }
     return true;
 }
@@ -312,7 +314,8 @@ MF_API int mf_create(const mf_csr_t *g, const int32_t *cap, int32_t s, int32_t t
     h->max_rounds = o.max_rounds > 0 ? o.max_rounds : 65536;
     h->relabel_budget = o.relabel_budget > 0 ? o.relabel_budget : std::max<int64_t>(1024, n / 2);
     h->rounds_per_level = o.rounds_per_level == 0 ? 2 : (o.rounds_per_level < 0 ? 0 : o.rounds_per_level);
-    h->use_gap = (o.flags & MF_FLAG_NO_GAP) ? 0 : 1;
+    h->use_gap = (o.flags & MF_FLAG_GAP) ? 1 : 0;
+    h->stall_rounds = o.stall_rounds == 0 ? 3 : (o.stall_rounds < 0 ? 0 : o.stall_rounds);
     h->kc = o.kernel_cycles > 0 ? o.kernel_cycles
                                 : (int32_t)std::max<int64_t>(1, (int64_t)((double)m / n + 0.5));
     auto bail = [&](int code, const std::string &msg) {

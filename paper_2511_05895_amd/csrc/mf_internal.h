@@ -24,11 +24,12 @@ enum : int {
     kTrLevels = 0,   // BFS levels of the global relabel that opened the phase
     kTrActive,       // active vertices it found
     kTrRounds,       // push/relabel rounds run
-    kTrReason,       // why the phase ended: 0 no active vertex left, 1 round cap, 2 relabel budget
+    kTrReason,       // why the phase ended: 0 no active vertex left, 1 round cap, 2 relabel budget,
+                     // 3 no excess delivered for max(stall_rounds, levels) rounds
     kTrRelabels,     // relabels in the phase
     kTrRelabelled,   // distinct vertices relabelled
     kTrPushes,       // pushes in the phase
-    kTrSpare
+    kTrLastDeliv     // last round in which excess reached t or a deficient vertex
 };
 
 // Loop status written by the persistent kernel.
@@ -88,6 +89,7 @@ struct Ctrl {
     int32_t pad_;
     int64_t phase_relabels;  // relabels of the current phase
     int64_t phase_pushes;    // pushes of the current phase
+    int64_t phase_deliv;     // excess delivered into t or deficient vertices this phase
     int32_t ntrace;          // phases recorded in trace[]
     int32_t gap;             // lowest height found empty in this phase (|V| = none)
     int32_t trace[kTraceCap][kTraceFields];
@@ -135,6 +137,8 @@ struct LoopParams {
     int32_t rounds_per_level;  // > 0: a phase also stops after this many rounds per
                                // level of the BFS that started it (+16)
     int32_t use_gap;           // gap heuristic on (1) or off (0)
+    int32_t stall_rounds;      // > 0: a phase ends after max(this, BFS levels) rounds without delivery
+    int32_t pad_;
 };
 
 // ---- launch wrappers (mf_kernels.hip) ----

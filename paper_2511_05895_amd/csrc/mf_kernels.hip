@@ -188,6 +188,7 @@ __device__ bool grid_barrier(Ctrl *c, int64_t limit) {
 // end of every loop round and of the kernel, then cleared.
 struct Tally {
     uint32_t bfs_v = 0, bfs_a = 0, pr_cyc = 0, pr_a = 0, push = 0, relabel = 0, rie_a = 0, rie_sat = 0;
+    int64_t deliv = 0;  // excess this lane delivered into deficient vertices (per round)
 };
 
 // Every thread of the workgroup must call it.
@@ -398,13 +399,14 @@ __device__ __forceinline__ int relabel_to(const DevGraph &g, int u, int ho, int 
 // subtracted by the caller (one atomic per visit chunk).
 template <int SC>
 __device__ __forceinline__ void push_arc(const DevGraph &g, const RoundCtx &rc, int a, int v,
-                                         int32_t d, int64_t &to_t) {
+                                         int32_t d, int64_t &to_t, Tally &tl) {
     add<SC>(cf_ptr(g.arc, a), -d);
     add<SC>(cf_ptr(g.arc, g.twin[a]), d);
     if (v == g.t) {
         to_t += d;
     } else {
         const int64_t old = fetch_add<SC>(&g.e[v], (int64_t)d);
+        if (old < 0) tl.deliv += min((int64_t)d, -old);  // part of a deficit filled
         if (old <= 0 && old + d > 0 && v != g.s) list_add<SC>(g, rc, v);
     }
 }
@@ -441,7 +443,7 @@ __device__ int discharge_lane(const DevGraph &g, int u, int kc, const RoundCtx &
                 const int32_t cfl = ld<SC>(cf_ptr(g.arc, a));
                 const int64_t d = min(eu - sent, (int64_t)cfl);
                 if (d <= 0) continue;
-                push_arc<SC>(g, rc, a, r.x, (int32_t)d, to_t);
+                push_arc<SC>(g, rc, a, r.x, (int32_t)d, to_t, tl);
                 sent += d;
                 tl.push++;
             }
@@ -514,7 +516,7 @@ __device__ int discharge_wave(const DevGraph &g, int u, int kc, const RoundCtx &
                 const int64_t excl = incl - c;
                 const int64_t d = (c > 0 && excl < room) ? min(c, room - excl) : 0;
                 if (d > 0) {
-                    push_arc<SC>(g, rc, a, v, (int32_t)d, to_t);
+                    push_arc<SC>(g, rc, a, v, (int32_t)d, to_t, tl);
                     tl.push++;
                 }
                 const int64_t tot = min(__shfl(incl, 63, 64), room);
@@ -540,16 +542,21 @@ __device__ int discharge_wave(const DevGraph &g, int u, int kc, const RoundCtx &
 template <int SC>
 __device__ __forceinline__ void flush_to_t(const DevGraph &g, int64_t &to_t) {
     const int64_t s = wave_sum(to_t);
-    if (lane_id() == 0 && s) add<SC>(&g.e[g.t], s);
+    if (lane_id() == 0 && s) {
+        add<SC>(&g.e[g.t], s);
+        add<SC>(&g.ctrl->phase_deliv, s);
+    }
     to_t = 0;
 }
 
 template <int SC>
-__device__ __forceinline__ void flush_relabels(Ctrl *c, int64_t &rl, int64_t pushes) {
+__device__ __forceinline__ void flush_relabels(Ctrl *c, int64_t &rl, int64_t pushes, int64_t deliv) {
     const int64_t s = wave_sum(rl);
     const int64_t p = wave_sum(pushes);
+    const int64_t dv = wave_sum(deliv);
     if (lane_id() == 0 && s) add<SC>(&c->phase_relabels, s);
     if (lane_id() == 0 && p) add<SC>(&c->phase_pushes, p);
+    if (lane_id() == 0 && dv) add<SC>(&c->phase_deliv, dv);
     rl = 0;
 }
 
@@ -574,7 +581,8 @@ __device__ void pr_round(const DevGraph &g, int rd, int nl, int nh, int kc, cons
         rl += discharge_wave<SC>(g, lst[g.n - 1 - idx], kc, rc, tl, to_t);
     }
     flush_to_t<SC>(g, to_t);
-    flush_relabels<SC>(g.ctrl, rl, (int64_t)(tl.push - push0));
+    flush_relabels<SC>(g.ctrl, rl, (int64_t)(tl.push - push0), tl.deliv);
+    tl.deliv = 0;
 }
 
 // One topology-driven round: every vertex is visited (idle when inactive).
@@ -597,7 +605,8 @@ __device__ void pr_round_topology(const DevGraph &g, int kc, const RoundCtx &rc,
     for (int64_t i = gwave; i < g.n_heavy_all; i += nwaves)
         rl += discharge_wave<SC>(g, g.heavy_all[i], kc, rc, tl, to_t);
     flush_to_t<SC>(g, to_t);
-    flush_relabels<SC>(g.ctrl, rl, (int64_t)(tl.push - push0));
+    flush_relabels<SC>(g.ctrl, rl, (int64_t)(tl.push - push0), tl.deliv);
+    tl.deliv = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -690,6 +699,7 @@ __global__ void __launch_bounds__(BLOCK) k_loop(DevGraph g, LoopParams p) {
             c->nrelab = 0;
             c->phase_relabels = 0;
             c->phase_pushes = 0;
+            c->phase_deliv = 0;
             c->gap = g.n;
             add<SC>(&c->stat[kStGlobalRelabels], 1);
         }
@@ -729,6 +739,8 @@ __global__ void __launch_bounds__(BLOCK) k_loop(DevGraph g, LoopParams p) {
                                                      : p.max_rounds;
         const int active0 = ld<SC>(&c->lst[0].light) + ld<SC>(&c->lst[0].heavy);
         int r = 0, reason = 0;
+        int64_t last_deliv = -1;
+        int last_change = 0;
         for (;; ++r) {
             const int rd = r % 3, wr = (r + 1) % 3, rs = (r + 2) % 3;
             const int nl = ld<SC>(&c->lst[rd].light);
@@ -740,6 +752,17 @@ __global__ void __launch_bounds__(BLOCK) k_loop(DevGraph g, LoopParams p) {
             }
             if (ld<SC>(&c->phase_relabels) > p.relabel_budget) {
                 reason = 2;
+                break;
+            }
+            // all values read here were written before the last barrier, so
+            // every workgroup takes the same decision
+            const int64_t dl = ld<SC>(&c->phase_deliv);
+            if (dl != last_deliv) {
+                last_deliv = dl;
+                last_change = r;
+            }
+            if (p.stall_rounds > 0 && r - last_change >= max(p.stall_rounds, L)) {
+                reason = 3;
                 break;
             }
             if (leader) c->lst[rs] = ListCtr{0, 0, 0, 0};
@@ -765,7 +788,7 @@ __global__ void __launch_bounds__(BLOCK) k_loop(DevGraph g, LoopParams p) {
                 tr_rec[kTrRelabels] = (int32_t)min<int64_t>(ld<SC>(&c->phase_relabels), INT32_MAX);
                 tr_rec[kTrRelabelled] = nrel;
                 tr_rec[kTrPushes] = (int32_t)min<int64_t>(ld<SC>(&c->phase_pushes), INT32_MAX);
-                tr_rec[kTrSpare] = 0;
+                tr_rec[kTrLastDeliv] = last_change;
                 c->ntrace++;
             }
         }

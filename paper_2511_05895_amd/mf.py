@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(_HERE, "libmf.so")
 
 MF_OK, MF_EINVAL, MF_ENOMEM, MF_EDEVICE, MF_ESTATE, MF_ETIMEOUT = range(6)
 MF_MODE_DATA, MF_MODE_TOPOLOGY = 0, 1
-MF_FLAG_NO_GAP = 1
+MF_FLAG_GAP = 1
 _NAMES = {1: "MF_EINVAL", 2: "MF_ENOMEM", 3: "MF_EDEVICE", 4: "MF_ESTATE", 5: "MF_ETIMEOUT"}
 
 
@@ -32,7 +32,7 @@ class mf_opts_t(C.Structure):
     _fields_ = [("kernel_cycles", C.c_int32), ("mode", C.c_int32), ("grid_blocks", C.c_int32),
                 ("device", C.c_int32), ("max_iterations", C.c_int64), ("time_budget_ms", C.c_int32),
                 ("max_rounds", C.c_int32), ("relabel_budget", C.c_int32), ("rounds_per_level", C.c_int32),
-                ("flags", C.c_int32), ("reserved", C.c_int32 * 3)]
+                ("flags", C.c_int32), ("stall_rounds", C.c_int32), ("reserved", C.c_int32 * 2)]
 
 
 class mf_stats_t(C.Structure):
@@ -214,7 +214,7 @@ def mf_export_state(h, n: int, m: int):
     return cap[:A], cf[:A], e, hgt, ecap[:m]
 
 
-TRACE_FIELDS = ("levels", "active", "rounds", "reason", "relabels", "relabelled", "pushes", "spare")
+TRACE_FIELDS = ("levels", "active", "rounds", "reason", "relabels", "relabelled", "pushes", "last_delivery")
 
 
 def mf_get_trace(h, max_phases: int = 256) -> np.ndarray:
@@ -236,13 +236,14 @@ class MaxFlow:
 
     def __init__(self, g, kernel_cycles=0, mode=MF_MODE_DATA, grid_blocks=0, max_iterations=-1,
                  device=0, cap=None, time_budget_ms=0, max_rounds=0, relabel_budget=0,
-                 rounds_per_level=0, flags=0):
+                 rounds_per_level=0, flags=0, stall_rounds=0):
         o = mf_default_opts()
         o.time_budget_ms = time_budget_ms
         o.max_rounds = max_rounds
         o.relabel_budget = relabel_budget
         o.rounds_per_level = rounds_per_level
         o.flags = flags
+        o.stall_rounds = stall_rounds
         o.kernel_cycles = kernel_cycles
         o.mode = mode
         o.grid_blocks = grid_blocks
