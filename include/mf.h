@@ -238,6 +238,94 @@ MF_API int mf_get_trace(const mf_handle_t *h, int32_t *out, int32_t max_phases, 
  * handle's own stream). */
 MF_API int mf_set_stream(mf_handle_t *h, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Batched solve of many independent instances.
+ *
+ * Each instance is its own directed graph with its own s and t, solved from
+ * scratch (the static method of Alg. 1: saturate the source, then global
+ * relabel / push-relabel / RemoveInvalidEdges until no active vertex is
+ * left).  The instances are packed block-diagonally into one set of device
+ * arrays and each is solved by ONE workgroup of a persistent launch, so no
+ * grid barrier is involved and workgroups never wait for each other.
+ * Instances are grouped by their number of residual arcs into size classes;
+ * each class is one launch with its own workgroup size and KERNELCYCLES,
+ * instances ordered largest first inside it; the classes run side by side.
+ * With use_graph the launches are captured into a hipGraph on the first solve
+ * after a configuration change and that graph is replayed by later solves.
+ * Values and cuts follow the same definitions as for a single handle.
+ * ------------------------------------------------------------------------ */
+#define MF_BATCH_MAX_CLASSES 4
+
+typedef struct mf_batch mf_batch_t;
+
+typedef struct {
+    int32_t device;
+    int32_t time_budget_ms;  /* per instance; 0 = 60 s                      */
+    int32_t n_classes;       /* 1..MF_BATCH_MAX_CLASSES (default 3)         */
+    int32_t use_graph;       /* 1 = capture once and replay (default), 0 = plain launches */
+    int64_t class_max_arcs[MF_BATCH_MAX_CLASSES]; /* class c takes the instances
+                                with at most this many residual arcs that no
+                                earlier class took; ascending; the last class
+                                takes the rest (default 32768, 262144)       */
+    int32_t block[MF_BATCH_MAX_CLASSES];         /* threads per workgroup of a
+                                class: 256, 512 or 1024 (default 256, 1024, 1024) */
+    int32_t kernel_cycles[MF_BATCH_MAX_CLASSES]; /* 0 = max(1, round(m/n)) per instance */
+    int32_t flags;           /* MF_FLAG_GAP                                   */
+    int32_t stall_rounds;    /* as in mf_opts_t                               */
+    int32_t reserved[2];     /* must be zero                                  */
+} mf_batch_opts_t;
+
+MF_API void mf_batch_default_opts(mf_batch_opts_t *opts);
+
+/* count instances.  Instance i has n[i] vertices and m[i] edges; its CSR rows
+ * are row_ptr[R_i .. R_i + n[i]] with R_i = sum_{j<i} (n[j] + 1), values local
+ * to the instance (0 .. m[i]); its edges are col[E_i .. E_i + m[i]) and
+ * cap[E_i ..] with E_i = sum_{j<i} m[j], col holding local vertex ids;
+ * source s[i], sink t[i].  Edge ids of instance i are 0 .. m[i]-1.  Every
+ * instance is checked as mf_create checks one graph (MF_EINVAL names the
+ * instance).  Host arrays are read during the call only.  Does not solve. */
+MF_API int mf_batch_create(int32_t count, const int32_t *n, const int64_t *m, const int64_t *row_ptr,
+                           const int32_t *col, const int32_t *cap, const int32_t *s, const int32_t *t,
+                           const mf_batch_opts_t *opts, mf_batch_t **out);
+MF_API void mf_batch_destroy(mf_batch_t *b);
+MF_API const char *mf_batch_last_error(const mf_batch_t *b);
+MF_API int mf_batch_count(const mf_batch_t *b, int32_t *count);
+MF_API int mf_batch_get_opts(const mf_batch_t *b, mf_batch_opts_t *opts);
+/* New class split / workgroup sizes / cycles; the captured graph is rebuilt
+ * by the next solve.  The device cannot change. */
+MF_API int mf_batch_set_opts(mf_batch_t *b, const mf_batch_opts_t *opts);
+
+/* Solve every instance from scratch on its current capacities.  MF_ETIMEOUT
+ * when an instance ran out of its time budget, MF_EDEVICE on a device error;
+ * the values of the call are then not available. */
+MF_API int mf_batch_solve(mf_batch_t *b);
+/* Solve only the instances of class `cls`, as one plain launch on the batch's
+ * stream; *kernel_ms receives the launch's event-timed duration. */
+MF_API int mf_batch_solve_class(mf_batch_t *b, int32_t cls, double *kernel_ms);
+/* For every non-empty class, time each workgroup size (256, 512, 1024) x
+ * KERNELCYCLES (per instance default, 1, 2, 4) with `repeats` class-alone
+ * launches, keep the fastest median, and adopt the result; every candidate
+ * must reach the same values (else MF_EDEVICE).  *chosen (may be NULL)
+ * receives the adopted options.  Leaves the batch unsolved. */
+MF_API int mf_batch_autotune(mf_batch_t *b, int32_t repeats, mf_batch_opts_t *chosen);
+
+/* Residual arcs of every instance (int64[count]), after merging. */
+MF_API int mf_batch_num_arcs(const mf_batch_t *b, int64_t *arcs);
+/* values int64[count] of the last solve (MF_ESTATE before one). */
+MF_API int mf_batch_values(const mf_batch_t *b, int64_t *values);
+/* Event-timed duration of the last solve (all classes, fork to join). */
+MF_API int mf_batch_last_ms(const mf_batch_t *b, double *kernel_ms);
+/* Canonical minimum cut of instance i, as mf_min_cut (side uint8[n[i]], may
+ * be NULL). */
+MF_API int mf_batch_min_cut(mf_batch_t *b, int32_t i, uint8_t *side, int64_t *cut_cap);
+/* Counters of instance i in its last solve. */
+MF_API int mf_batch_get_stats(mf_batch_t *b, int32_t i, mf_stats_t *stats);
+/* New absolute capacities for edges of instance i (local ids, distinct, in
+ * [0, m[i]); capacities within that instance's per-edge limit); the next
+ * solve uses them.  A rejected batch (MF_EINVAL) changes nothing. */
+MF_API int mf_batch_set_capacities(mf_batch_t *b, int32_t i, const int64_t *edge_ids,
+                                   const int32_t *new_caps, int64_t k);
+
 #ifdef __cplusplus
 }
 #endif

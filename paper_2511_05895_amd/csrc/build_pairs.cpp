@@ -15,6 +15,32 @@
 
 namespace mf {
 
+int check_graph(int32_t n, int64_t m, const int64_t *row_ptr, const int32_t *col, const int32_t *cap,
+                int32_t s, int32_t t, std::string *err) {
+    auto bad = [&](const char *why) {
+        *err = why;
+        return -1;
+    };
+    if (n < 2) return bad("n must be >= 2");
+    if (m < 0 || m >= (int64_t)INT32_MAX) return bad("m must be in [0, 2^31-1)");
+    if (s < 0 || s >= n || t < 0 || t >= n) return bad("s or t out of range");
+    if (s == t) return bad("s == t");
+    if (!row_ptr || (m > 0 && (!col || !cap))) return bad("null graph or capacity array");
+    if (row_ptr[0] != 0 || row_ptr[n] != m) return bad("row_ptr must run from 0 to m");
+    for (int32_t v = 0; v < n; ++v)
+        if (row_ptr[v + 1] < row_ptr[v]) return bad("row_ptr not non-decreasing");
+    for (int64_t i = 0; i < m; ++i) {
+        if (col[i] < 0 || col[i] >= n) return bad("col out of range");
+        if (cap[i] < 0) return bad("negative capacity");
+    }
+    return 0;
+}
+
+int64_t edge_cap_limit(int32_t mult) {
+    const int64_t lim = (int64_t)INT32_MAX / (2 * (int64_t)(mult > 0 ? mult : 1));
+    return lim < (1ll << 30) ? lim : (1ll << 30);
+}
+
 int build_pairs(int32_t n, int64_t m, const int64_t *row_ptr, const int32_t *col, const int32_t *cap,
                 HostPairs *out, std::string *err) {
     // half-edges: for edge i (u -> v, u != v) one entry owned by u (forward) and

@@ -20,6 +20,17 @@ struct HostPairs {
     int32_t max_pair_mult = 1;      // most input edges sharing one arc pair
 };
 
+// Argument checks of one graph: n >= 2, s and t distinct and in range,
+// row_ptr non-decreasing from 0 to m < 2^31-1, col in [0, n), cap >= 0.
+// Returns 0, or -1 with *err set.
+int check_graph(int32_t n, int64_t m, const int64_t *row_ptr, const int32_t *col, const int32_t *cap,
+                int32_t s, int32_t t, std::string *err);
+
+// Per-edge capacity limit of a layout whose busiest arc pair merges `mult`
+// input edges: after the deltas of one batch land, an arc's residual is at
+// most twice the pair's capacity sum, which must fit int32.
+int64_t edge_cap_limit(int32_t mult);
+
 // Inputs must already be validated (row_ptr monotone 0..m, col in range,
 // cap >= 0).  Returns 0, or -1 with *err set.
 int build_pairs(int32_t n, int64_t m, const int64_t *row_ptr, const int32_t *col, const int32_t *cap,

@@ -13,6 +13,7 @@
 
 #include "../../include/mf.h"
 #include "build_pairs.h"
+#include "ctrl_stats.h"
 #include "mf_internal.h"
 
 namespace {
@@ -108,28 +109,9 @@ int finish_call(mf_handle_t *h) {
 }
 
 void fill_stats(mf_handle_t *h, bool ran_loop) {
-    const mf::Ctrl &c = *h->h_ctrl;
     mf_stats_t &s = h->stats;
-    std::memset(&s, 0, sizeof(s));
-    s.iterations = c.stat[mf::kStIterations];
-    s.global_relabels = c.stat[mf::kStGlobalRelabels];
-    s.bfs_levels = c.stat[mf::kStLevels];
-    s.bfs_vertices = c.stat[mf::kStBfsVertices];
-    s.bfs_arcs = c.stat[mf::kStBfsArcs];
-    s.pr_vertex_cycles = c.stat[mf::kStPrCycles];
-    s.pr_arcs = c.stat[mf::kStPrArcs];
-    s.pushes = c.stat[mf::kStPushes];
-    s.relabels = c.stat[mf::kStRelabels];
-    s.rie_arcs = c.stat[mf::kStRieArcs];
-    s.rie_saturations = c.stat[mf::kStRieSat];
-    s.updates = c.stat[mf::kStUpdates];
-    s.clamps = c.stat[mf::kStClamps];
-    s.source_pushes = c.stat[mf::kStSourcePushes];
-    s.rounds = c.stat[mf::kStRounds];
+    mf::stats_from_ctrl(*h->h_ctrl, h->tick_ms, &s);
     s.grid_blocks = h->grid;
-    s.bfs_ms = c.stat[mf::kStBfsTicks] * h->tick_ms;
-    s.pr_ms = c.stat[mf::kStPrTicks] * h->tick_ms;
-    s.rie_ms = c.stat[mf::kStRieTicks] * h->tick_ms;
     if (ran_loop) {
         float ms = 0.f;
         s.loop_launches = 1;
@@ -272,23 +254,12 @@ MF_API int mf_create(const mf_csr_t *g, const int32_t *cap, int32_t s, int32_t t
         return fail(nullptr, MF_EINVAL, "null graph or capacity array");
     const int32_t n = g->n;
     const int64_t m = g->m;
-    if (n < 2) return fail(nullptr, MF_EINVAL, "n must be >= 2");
-    if (m < 0 || m >= (int64_t)INT32_MAX) return fail(nullptr, MF_EINVAL, "m must be in [0, 2^31-1)");
-    if (s < 0 || s >= n || t < 0 || t >= n) return fail(nullptr, MF_EINVAL, "s or t out of range");
-    if (s == t) return fail(nullptr, MF_EINVAL, "s == t");
+    std::string why;
+    if (mf::check_graph(n, m, g->row_ptr, g->col, cap, s, t, &why)) return fail(nullptr, MF_EINVAL, why);
     mf_opts_t o;
     mf_default_opts(&o);
     if (opts) o = *opts;
-    std::string why;
     if (!opts_valid(o, &why)) return fail(nullptr, MF_EINVAL, why);
-    if (g->row_ptr[0] != 0 || g->row_ptr[n] != m)
-        return fail(nullptr, MF_EINVAL, "row_ptr must run from 0 to m");
-    for (int32_t v = 0; v < n; ++v)
-        if (g->row_ptr[v + 1] < g->row_ptr[v]) return fail(nullptr, MF_EINVAL, "row_ptr not non-decreasing");
-    for (int64_t i = 0; i < m; ++i) {
-        if (g->col[i] < 0 || g->col[i] >= n) return fail(nullptr, MF_EINVAL, "col out of range");
-        if (cap[i] < 0) return fail(nullptr, MF_EINVAL, "negative capacity");
-    }
     mf::HostPairs hp;
     try {
         if (mf::build_pairs(n, m, g->row_ptr, g->col, cap, &hp, &why))
@@ -298,7 +269,7 @@ MF_API int mf_create(const mf_csr_t *g, const int32_t *cap, int32_t s, int32_t t
     }
     // per-edge capacity limit: after the deltas of one batch land, an arc's
     // residual is at most twice the pair's capacity sum, which must fit int32
-    const int64_t lim = std::min<int64_t>(1ll << 30, (int64_t)INT32_MAX / (2 * (int64_t)hp.max_pair_mult));
+    const int64_t lim = mf::edge_cap_limit(hp.max_pair_mult);
     for (int64_t i = 0; i < m; ++i)
         if (cap[i] > lim)
             return fail(nullptr, MF_EINVAL,

@@ -141,6 +141,13 @@ struct LoopParams {
     int32_t pad_;
 };
 
+// Result of one instance of a batched solve.
+struct BatchResult {
+    int64_t value;   // e(t) plus the deficits
+    int32_t status;  // loop status (kSolved, kDeadline, ...)
+    int32_t pad;
+};
+
 // ---- launch wrappers (mf_kernels.hip) ----
 hipError_t launch_reset_ctrl(const DevGraph &g, hipStream_t st);
 hipError_t launch_init_state(const DevGraph &g, hipStream_t st);
@@ -152,6 +159,11 @@ hipError_t launch_apply_delta(const DevGraph &g, const int64_t *ids, const int32
 hipError_t launch_clamp(const DevGraph &g, const int64_t *ids, int64_t k, hipStream_t st);
 hipError_t launch_loop(const DevGraph &g, const LoopParams &p, int grid, hipStream_t st);
 hipError_t launch_min_cut(const DevGraph &g, uint8_t *d_side, hipStream_t st);
+// Batched solve: `count` workgroups of `block` threads (256, 512 or 1024);
+// workgroup j solves instance order[j] of graphs[] from scratch with
+// KERNELCYCLES kc[order[j]] and writes res[order[j]].
+hipError_t launch_batch(const DevGraph *graphs, const int32_t *order, int count, const LoopParams &p,
+                        const int32_t *kc, BatchResult *res, int block, hipStream_t st);
 hipError_t launch_fill_i32(int32_t *p, int64_t count, int32_t value, hipStream_t st);
 // Largest co-resident workgroup count of the loop kernel.
 hipError_t loop_max_coresident(int device, int *blocks);

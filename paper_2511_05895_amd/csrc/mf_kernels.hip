@@ -140,11 +140,22 @@ __device__ __forceinline__ int wave_appendn(int32_t *counter, int c) {
 
 __device__ __forceinline__ int n_items(int deg) { return (deg + kChunk - 1) / kChunk; }
 
-// Grid-wide barrier with a bounded wait.  Returns false when the wait ran out
+// The workgroups that run one solve loop together: ranks 0..size-1.  Either
+// the whole grid of a cooperative launch, or a single workgroup of a batched
+// launch (then every barrier is a workgroup barrier).
+struct Team {
+    int rank, size;
+    __device__ int64_t tid() const { return (int64_t)rank * blockDim.x + threadIdx.x; }
+    __device__ int64_t nthreads() const { return (int64_t)size * blockDim.x; }
+    __device__ int64_t wave() const { return (int64_t)rank * (blockDim.x >> 6) + (threadIdx.x >> 6); }
+    __device__ int64_t nwaves() const { return (int64_t)size * (blockDim.x >> 6); }
+};
+
+// Barrier of a team with a bounded wait.  Returns false when the wait ran out
 // (wall clock, `limit` ticks) or another workgroup aborted; the caller must then
 // leave the kernel, so every workgroup ends even if co-residency ever failed.
-__device__ bool grid_barrier(Ctrl *c, int64_t limit) {
-    if (gridDim.x == 1) {
+__device__ bool grid_barrier(Ctrl *c, const Team &tm, int64_t limit) {
+    if (tm.size == 1) {
         __syncthreads();
         return true;
     }
@@ -156,7 +167,7 @@ __device__ bool grid_barrier(Ctrl *c, int64_t limit) {
         uint32_t gen = __hip_atomic_load(&c->bar_gen.v, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
         uint32_t arrived =
             __hip_atomic_fetch_add(&c->bar_count.v, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        if (arrived == gridDim.x - 1) {
+        if (arrived == (uint32_t)tm.size - 1) {
             __hip_atomic_store(&c->bar_count.v, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_store(&c->bar_gen.v, gen + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         } else {
@@ -217,9 +228,9 @@ __device__ void flush_tally(Ctrl *c, Tally &t) {
 // Height reset: t and every deficient vertex other than s are roots (height
 // 0); all others get |V|.  Roots become the level-0 frontier.
 template <int SC>
-__device__ void bfs_roots(const DevGraph &g, Tally &tl) {
-    const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+__device__ void bfs_roots(const DevGraph &g, const Team &tm, Tally &tl) {
+    const int64_t gtid = tm.tid();
+    const int64_t stride = tm.nthreads();
     const int64_t nr = ((int64_t)g.n + 63) & ~63ll;
     for (int64_t i = gtid; i < nr; i += stride) {
         const int v = (int)i;
@@ -249,15 +260,14 @@ __device__ void bfs_roots(const DevGraph &g, Tally &tl) {
 // frontier items of the next level; those with positive excess go to the
 // active worklist (A of Alg. 1: e > 0 and h < |V|, s and t excluded).
 template <int SC>
-__device__ void bfs_level(const DevGraph &g, int L, Tally &tl) {
+__device__ void bfs_level(const DevGraph &g, const Team &tm, int L, Tally &tl) {
     const int2 *__restrict__ qin = g.q[L & 1];
     int2 *qout = g.q[(L + 1) & 1];
     const int cnt = ld<SC>(&g.ctrl->qcount[L % 3]);
     int32_t *qout_count = &g.ctrl->qcount[(L + 1) % 3];
     const int lane = lane_id();
-    const int64_t wpb = blockDim.x >> 6;
-    const int64_t gwave = (int64_t)blockIdx.x * wpb + (threadIdx.x >> 6);
-    const int64_t nwaves = (int64_t)gridDim.x * wpb;
+    const int64_t gwave = tm.wave();
+    const int64_t nwaves = tm.nwaves();
     const int n = g.n;
     for (int64_t base = gwave * 64; base < cnt; base += nwaves * 64) {
         const int64_t idx = base + lane;
@@ -563,10 +573,10 @@ __device__ __forceinline__ void flush_relabels(Ctrl *c, int64_t &rl, int64_t pus
 // One data-driven round over list rd: short lists by lane, long ones by
 // wavefronts that take the next vertex from a shared counter.
 template <int SC>
-__device__ void pr_round(const DevGraph &g, int rd, int nl, int nh, int kc, const RoundCtx &rc,
-                         Tally &tl) {
-    const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+__device__ void pr_round(const DevGraph &g, const Team &tm, int rd, int nl, int nh, int kc,
+                         const RoundCtx &rc, Tally &tl) {
+    const int64_t gtid = tm.tid();
+    const int64_t stride = tm.nthreads();
     const int32_t *lst = g.list[rd];
     int64_t to_t = 0, rl = 0;
     const uint32_t push0 = tl.push;
@@ -587,9 +597,10 @@ __device__ void pr_round(const DevGraph &g, int rd, int nl, int nh, int kc, cons
 
 // One topology-driven round: every vertex is visited (idle when inactive).
 template <int SC>
-__device__ void pr_round_topology(const DevGraph &g, int kc, const RoundCtx &rc, Tally &tl) {
-    const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+__device__ void pr_round_topology(const DevGraph &g, const Team &tm, int kc, const RoundCtx &rc,
+                                  Tally &tl) {
+    const int64_t gtid = tm.tid();
+    const int64_t stride = tm.nthreads();
     int64_t to_t = 0, rl = 0;
     const uint32_t push0 = tl.push;
     for (int64_t i = gtid; i < g.n; i += stride) {
@@ -599,10 +610,7 @@ __device__ void pr_round_topology(const DevGraph &g, int kc, const RoundCtx &rc,
         rl += discharge_lane<SC>(g, u, kc, rc, tl, to_t);
     }
     flush_to_t<SC>(g, to_t);
-    const int64_t wpb = blockDim.x >> 6;
-    const int64_t gwave = (int64_t)blockIdx.x * wpb + (threadIdx.x >> 6);
-    const int64_t nwaves = (int64_t)gridDim.x * wpb;
-    for (int64_t i = gwave; i < g.n_heavy_all; i += nwaves)
+    for (int64_t i = tm.wave(); i < g.n_heavy_all; i += tm.nwaves())
         rl += discharge_wave<SC>(g, g.heavy_all[i], kc, rc, tl, to_t);
     flush_to_t<SC>(g, to_t);
     flush_relabels<SC>(g.ctrl, rl, (int64_t)(tl.push - push0), tl.deliv);
@@ -636,10 +644,10 @@ __device__ __forceinline__ void rie_arc(const DevGraph &g, int u, int hu, int a,
 // would push flow out of the source side and create deficits (new roots)
 // there, undoing the cut.
 template <int SC>
-__device__ void remove_invalid(const DevGraph &g, const int32_t *list, int64_t count, bool skip_cut,
-                               Tally &tl) {
-    const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+__device__ void remove_invalid(const DevGraph &g, const Team &tm, const int32_t *list, int64_t count,
+                               bool skip_cut, Tally &tl) {
+    const int64_t gtid = tm.tid();
+    const int64_t stride = tm.nthreads();
     const int64_t cr = (count + 63) & ~63ll;
     const int lane = lane_id();
     for (int64_t i = gtid; i < cr; i += stride) {
@@ -677,12 +685,12 @@ __device__ void remove_invalid(const DevGraph &g, const int32_t *list, int64_t c
 // The persistent solve loop (Alg. 1 / Alg. 4 while-loop)
 // ---------------------------------------------------------------------------
 
-template <int BLOCK, int SC>
-__global__ void __launch_bounds__(BLOCK) k_loop(DevGraph g, LoopParams p) {
+template <int SC>
+__device__ void solve_loop(const DevGraph &g, const Team &tm, const LoopParams &p) {
     Ctrl *c = g.ctrl;
     if (ld<SC>(&c->err)) return;  // update batch rejected: leave the state alone
     Tally tl;
-    const bool leader = blockIdx.x == 0 && threadIdx.x == 0;
+    const bool leader = tm.rank == 0 && threadIdx.x == 0;
     const bool topology = p.mode == 1;
     int64_t iter = 0;
     const uint64_t t0 = wall_clock64();
@@ -704,15 +712,15 @@ __global__ void __launch_bounds__(BLOCK) k_loop(DevGraph g, LoopParams p) {
             add<SC>(&c->stat[kStGlobalRelabels], 1);
         }
         const uint64_t tb = wall_clock64();
-        bfs_roots<SC>(g, tl);
-        if (!grid_barrier(c, p.barrier_ticks)) return;
+        bfs_roots<SC>(g, tm, tl);
+        if (!grid_barrier(c, tm, p.barrier_ticks)) return;
         int L = 0;
         for (;;) {
             const int cnt = ld<SC>(&c->qcount[L % 3]);
             if (cnt == 0) break;
             if (leader) c->qcount[(L + 2) % 3] = 0;
-            bfs_level<SC>(g, L, tl);
-            if (!grid_barrier(c, p.barrier_ticks)) return;
+            bfs_level<SC>(g, tm, L, tl);
+            if (!grid_barrier(c, tm, p.barrier_ticks)) return;
             ++L;
         }
         const uint64_t tp = wall_clock64();
@@ -767,17 +775,15 @@ __global__ void __launch_bounds__(BLOCK) k_loop(DevGraph g, LoopParams p) {
             }
             if (leader) c->lst[rs] = ListCtr{0, 0, 0, 0};
             const RoundCtx rc{g.list[wr], &c->lst[wr], rbase + r + 1, rbase, p.use_gap != 0};
-            if (topology) pr_round_topology<SC>(g, p.kc, rc, tl);
-            else pr_round<SC>(g, rd, nl, nh, p.kc, rc, tl);
-            if (!grid_barrier(c, p.barrier_ticks)) return;
+            if (topology) pr_round_topology<SC>(g, tm, p.kc, rc, tl);
+            else pr_round<SC>(g, tm, rd, nl, nh, p.kc, rc, tl);
+            if (!grid_barrier(c, tm, p.barrier_ticks)) return;
         }
         // --- RemoveInvalidEdges over the vertices that relabelled ---
         const uint64_t tr = wall_clock64();
         const int nrel = ld<SC>(&c->nrelab);
-        remove_invalid<SC>(g, g.relab, nrel, p.use_gap != 0, tl);
-        for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= g.n;
-             i += (int64_t)gridDim.x * blockDim.x)
-            g.hcount[i] = 0;
+        remove_invalid<SC>(g, tm, g.relab, nrel, p.use_gap != 0, tl);
+        for (int64_t i = tm.tid(); i <= g.n; i += tm.nthreads()) g.hcount[i] = 0;
         {
             if (leader && c->ntrace < kTraceCap) {
                 int32_t *tr_rec = c->trace[c->ntrace];
@@ -804,7 +810,7 @@ __global__ void __launch_bounds__(BLOCK) k_loop(DevGraph g, LoopParams p) {
             if ((int64_t)(wall_clock64() - t0) > p.deadline_ticks) c->stop = 1;
         }
         flush_tally<SC>(c, tl);
-        if (!grid_barrier(c, p.barrier_ticks)) return;
+        if (!grid_barrier(c, tm, p.barrier_ticks)) return;
         ++iter;
     }
     // --- value: e(t) plus the deficits of vertices other than s and t ---
@@ -814,8 +820,7 @@ __global__ void __launch_bounds__(BLOCK) k_loop(DevGraph g, LoopParams p) {
         if (threadIdx.x == 0) s_def = 0;
         __syncthreads();
         int64_t part = 0;
-        for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < g.n;
-             v += (int64_t)gridDim.x * blockDim.x) {
+        for (int64_t v = tm.tid(); v < g.n; v += tm.nthreads()) {
             const int64_t ev = g.e[v];
             if (ev < 0 && v != g.s && v != g.t) part += ev;
         }
@@ -826,6 +831,12 @@ __global__ void __launch_bounds__(BLOCK) k_loop(DevGraph g, LoopParams p) {
         if (leader) c->e_t = g.e[g.t];
     }
     flush_tally<SC>(c, tl);
+}
+
+// The whole grid is one team (cooperative launch), or a single workgroup.
+template <int BLOCK, int SC>
+__global__ void __launch_bounds__(BLOCK) k_loop(DevGraph g, LoopParams p) {
+    solve_loop<SC>(g, Team{(int)blockIdx.x, (int)gridDim.x}, p);
 }
 
 // ---------------------------------------------------------------------------
@@ -852,8 +863,9 @@ __global__ void k_init_state(DevGraph g) {
 // Saturate every residual arc out of s: c_f(s,u) -> 0, the twin gains it,
 // e(u) += d, e(s) -= d (Alg. 1 third loop; Alg. 4 lines 3-8, where the
 // remaining residual is pushed rather than e(u) overwritten).
-__global__ void k_saturate_source(DevGraph g) {
-    if (ld<kAgent>(&g.ctrl->err)) return;
+template <int SC>
+__device__ void saturate_source(const DevGraph &g, const Team &tm) {
+    if (ld<SC>(&g.ctrl->err)) return;
     __shared__ int64_t s_sum, s_cnt;
     if (threadIdx.x == 0) {
         s_sum = 0;
@@ -862,13 +874,12 @@ __global__ void k_saturate_source(DevGraph g) {
     __syncthreads();
     const int beg = g.row_ptr[g.s], end = g.row_ptr[g.s + 1];
     int64_t sum = 0, cnt = 0;
-    for (int64_t a = beg + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; a < end;
-         a += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t a = beg + tm.tid(); a < end; a += tm.nthreads()) {
         const int2 r = g.arc[a];
         if (r.y > 0) {
             g.arc[a].y = 0;
-            add<kAgent>(cf_ptr(g.arc, g.twin[a]), r.y);
-            add<kAgent>(&g.e[r.x], (int64_t)r.y);
+            add<SC>(cf_ptr(g.arc, g.twin[a]), r.y);
+            add<SC>(&g.e[r.x], (int64_t)r.y);
             sum += r.y;
             cnt++;
         }
@@ -881,9 +892,13 @@ __global__ void k_saturate_source(DevGraph g) {
     }
     __syncthreads();
     if (threadIdx.x == 0 && s_sum) {
-        add<kAgent>(&g.e[g.s], -s_sum);
-        add<kAgent>(&g.ctrl->stat[kStSourcePushes], s_cnt);
+        add<SC>(&g.e[g.s], -s_sum);
+        add<SC>(&g.ctrl->stat[kStSourcePushes], s_cnt);
     }
+}
+
+__global__ void k_saturate_source(DevGraph g) {
+    saturate_source<kAgent>(g, Team{(int)blockIdx.x, (int)gridDim.x});
 }
 
 // Batch validation: ids in [0, m), capacities in [0, cap_limit], ids distinct
@@ -985,6 +1000,54 @@ __global__ void k_fill_i32(int32_t *p, int64_t count, int32_t value) {
 }
 
 // ---------------------------------------------------------------------------
+// Batched solve: one workgroup per instance
+// ---------------------------------------------------------------------------
+
+// order[blockIdx.x] names the instance.  Its workgroup clears the control
+// block, stamps and per-height counts, initialises the state (c_f = c,
+// e = h = 0), saturates the source and runs the solve loop to the end, all
+// separated by workgroup barriers only; res[i] receives the value and the
+// loop status.  Workgroups never wait for each other.
+template <int BLOCK>
+__global__ void __launch_bounds__(BLOCK)
+    k_batch(const DevGraph *__restrict__ graphs, const int32_t *__restrict__ order, LoopParams p,
+            const int32_t *__restrict__ kc, BatchResult *__restrict__ res) {
+    const int i = order[blockIdx.x];
+    // a reference into the read-only table (uniform loads), not a private copy:
+    // the solve loop indexes the list and frontier pointer arrays dynamically
+    const DevGraph &g = graphs[i];
+    const Team tm{0, 1};
+    {
+        int *w = reinterpret_cast<int *>(g.ctrl);
+        const int words = (int)(sizeof(Ctrl) / sizeof(int));
+        for (int j = threadIdx.x; j < words; j += BLOCK) w[j] = 0;
+    }
+    for (int v = threadIdx.x; v < g.n; v += BLOCK) {
+        g.mark[v] = 0;
+        g.rmark[v] = 0;
+        g.e[v] = 0;
+        g.h[v] = 0;
+    }
+    for (int v = threadIdx.x; v <= g.n; v += BLOCK) g.hcount[v] = 0;
+    for (int a = threadIdx.x; a < g.A; a += BLOCK) g.arc[a].y = g.cap[a];
+    __syncthreads();
+    saturate_source<kGroup>(g, tm);
+    __syncthreads();
+    LoopParams q = p;
+    q.kc = kc[i];
+    if (q.relabel_budget <= 0) q.relabel_budget = max((int64_t)1024, (int64_t)g.n / 2);
+    solve_loop<kGroup>(g, tm, q);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        BatchResult r;
+        r.value = g.ctrl->e_t + g.ctrl->deficit;
+        r.status = g.ctrl->status;
+        r.pad = 0;
+        res[i] = r;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // launch wrappers
 // ---------------------------------------------------------------------------
 
@@ -1055,6 +1118,25 @@ hipError_t launch_loop(const DevGraph &g, const LoopParams &p, int grid, hipStre
     void *args[] = {&ga, &pa};
     return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_loop<kBlock, kAgent>), dim3(grid),
                                       dim3(kBlock), args, 0, st);
+}
+
+hipError_t launch_batch(const DevGraph *graphs, const int32_t *order, int count, const LoopParams &p,
+                        const int32_t *kc, BatchResult *res, int block, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    switch (block) {
+    case 256:
+        hipLaunchKernelGGL((k_batch<256>), dim3(count), dim3(256), 0, st, graphs, order, p, kc, res);
+        break;
+    case 512:
+        hipLaunchKernelGGL((k_batch<512>), dim3(count), dim3(512), 0, st, graphs, order, p, kc, res);
+        break;
+    case 1024:
+        hipLaunchKernelGGL((k_batch<1024>), dim3(count), dim3(1024), 0, st, graphs, order, p, kc, res);
+        break;
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_min_cut(const DevGraph &g, uint8_t *d_side, hipStream_t st) {

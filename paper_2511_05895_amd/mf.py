@@ -46,6 +46,24 @@ class mf_stats_t(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+MF_BATCH_MAX_CLASSES = 4
+
+
+class mf_batch_opts_t(C.Structure):
+    _fields_ = [("device", C.c_int32), ("time_budget_ms", C.c_int32), ("n_classes", C.c_int32),
+                ("use_graph", C.c_int32), ("class_max_arcs", C.c_int64 * MF_BATCH_MAX_CLASSES),
+                ("block", C.c_int32 * MF_BATCH_MAX_CLASSES),
+                ("kernel_cycles", C.c_int32 * MF_BATCH_MAX_CLASSES), ("flags", C.c_int32),
+                ("stall_rounds", C.c_int32), ("reserved", C.c_int32 * 2)]
+
+    def as_dict(self):
+        d = {}
+        for k, _ in self._fields_:
+            v = getattr(self, k)
+            d[k] = list(v) if hasattr(v, "__len__") else v
+        return d
+
+
 # Every symbol that include/mf.h declares, with its C signature.
 _SIGS = {
     "mf_default_opts": (None, [C.POINTER(mf_opts_t)]),
@@ -69,6 +87,24 @@ _SIGS = {
                                   C.c_void_p]),
     "mf_get_trace": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(C.c_int32)]),
     "mf_set_stream": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "mf_batch_default_opts": (None, [C.POINTER(mf_batch_opts_t)]),
+    "mf_batch_create": (C.c_int, [C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                  C.c_void_p, C.c_void_p, C.POINTER(mf_batch_opts_t),
+                                  C.POINTER(C.c_void_p)]),
+    "mf_batch_destroy": (None, [C.c_void_p]),
+    "mf_batch_last_error": (C.c_char_p, [C.c_void_p]),
+    "mf_batch_count": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32)]),
+    "mf_batch_get_opts": (C.c_int, [C.c_void_p, C.POINTER(mf_batch_opts_t)]),
+    "mf_batch_set_opts": (C.c_int, [C.c_void_p, C.POINTER(mf_batch_opts_t)]),
+    "mf_batch_solve": (C.c_int, [C.c_void_p]),
+    "mf_batch_solve_class": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_double)]),
+    "mf_batch_autotune": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(mf_batch_opts_t)]),
+    "mf_batch_values": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "mf_batch_num_arcs": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "mf_batch_last_ms": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
+    "mf_batch_min_cut": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.POINTER(C.c_int64)]),
+    "mf_batch_get_stats": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(mf_stats_t)]),
+    "mf_batch_set_capacities": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int64]),
 }
 
 _lib = None
@@ -317,6 +353,197 @@ class MaxFlow:
     @property
     def cap_limit(self) -> int:
         return mf_cap_limit(self.h)
+
+
+# ---------------- batched solve (mf_batch_*) ----------------
+
+def _bcheck(rc, b=None):
+    if rc != MF_OK:
+        msg = lib().mf_batch_last_error(b)
+        raise MfError(rc, msg.decode() if msg else "")
+    return rc
+
+
+def mf_batch_default_opts() -> mf_batch_opts_t:
+    o = mf_batch_opts_t()
+    lib().mf_batch_default_opts(C.byref(o))
+    return o
+
+
+def mf_batch_create(graphs, caps=None, opts: mf_batch_opts_t | None = None):
+    """graphs: objects with n, row_ptr, col, cap, s, t; caps: optional list of
+    per-instance capacity arrays.  Packs them block-diagonally."""
+    cnt = len(graphs)
+    n = np.array([g.n for g in graphs], dtype=np.int32)
+    m = np.array([g.col.shape[0] for g in graphs], dtype=np.int64)
+    rp = np.concatenate([np.asarray(g.row_ptr, dtype=np.int64) for g in graphs]) if cnt else np.zeros(0, np.int64)
+    col = np.concatenate([np.asarray(g.col, dtype=np.int32) for g in graphs] + [np.zeros(0, np.int32)])
+    cp = np.concatenate([np.asarray(g.cap if caps is None else caps[i], dtype=np.int32)
+                         for i, g in enumerate(graphs)] + [np.zeros(0, np.int32)])
+    s = np.array([g.s for g in graphs], dtype=np.int32)
+    t = np.array([g.t for g in graphs], dtype=np.int32)
+    out = C.c_void_p()
+    rc = lib().mf_batch_create(cnt, _ptr(n), _ptr(m), _ptr(rp), _ptr(col), _ptr(cp), _ptr(s), _ptr(t),
+                               C.byref(opts) if opts is not None else None, C.byref(out))
+    _bcheck(rc, None)
+    return out
+
+
+def mf_batch_destroy(b):
+    lib().mf_batch_destroy(b)
+
+
+def mf_batch_solve(b):
+    return _bcheck(lib().mf_batch_solve(b), b)
+
+
+def mf_batch_solve_class(b, cls: int) -> float:
+    ms = C.c_double()
+    _bcheck(lib().mf_batch_solve_class(b, int(cls), C.byref(ms)), b)
+    return float(ms.value)
+
+
+def mf_batch_autotune(b, repeats: int = 3) -> mf_batch_opts_t:
+    o = mf_batch_opts_t()
+    _bcheck(lib().mf_batch_autotune(b, int(repeats), C.byref(o)), b)
+    return o
+
+
+def mf_batch_get_opts(b) -> mf_batch_opts_t:
+    o = mf_batch_opts_t()
+    _bcheck(lib().mf_batch_get_opts(b, C.byref(o)), b)
+    return o
+
+
+def mf_batch_set_opts(b, o: mf_batch_opts_t):
+    return _bcheck(lib().mf_batch_set_opts(b, C.byref(o)), b)
+
+
+def mf_batch_count(b) -> int:
+    c = C.c_int32()
+    _bcheck(lib().mf_batch_count(b, C.byref(c)), b)
+    return int(c.value)
+
+
+def mf_batch_values(b) -> np.ndarray:
+    out = np.zeros(mf_batch_count(b), dtype=np.int64)
+    _bcheck(lib().mf_batch_values(b, _ptr(out)), b)
+    return out
+
+
+def mf_batch_num_arcs(b) -> np.ndarray:
+    out = np.zeros(mf_batch_count(b), dtype=np.int64)
+    _bcheck(lib().mf_batch_num_arcs(b, _ptr(out)), b)
+    return out
+
+
+def mf_batch_last_ms(b) -> float:
+    ms = C.c_double()
+    _bcheck(lib().mf_batch_last_ms(b, C.byref(ms)), b)
+    return float(ms.value)
+
+
+def mf_batch_min_cut(b, i: int, n: int):
+    side = np.zeros(n, dtype=np.uint8)
+    cut = C.c_int64()
+    _bcheck(lib().mf_batch_min_cut(b, int(i), _ptr(side), C.byref(cut)), b)
+    return side, int(cut.value)
+
+
+def mf_batch_get_stats(b, i: int) -> dict:
+    s = mf_stats_t()
+    _bcheck(lib().mf_batch_get_stats(b, int(i), C.byref(s)), b)
+    return s.as_dict()
+
+
+def mf_batch_set_capacities(b, i: int, edge_ids, new_caps):
+    ids = np.ascontiguousarray(edge_ids, dtype=np.int64)
+    caps = np.ascontiguousarray(new_caps, dtype=np.int32)
+    if ids.shape != caps.shape:
+        raise ValueError("edge_ids and new_caps differ in length")
+    return _bcheck(lib().mf_batch_set_capacities(b, int(i), _ptr(ids), _ptr(caps), ids.shape[0]), b)
+
+
+class Batch:
+    """Owns one batch of independent instances solved together."""
+
+    def __init__(self, graphs, caps=None, n_classes=None, class_max_arcs=None, block=None,
+                 kernel_cycles=None, use_graph=True, time_budget_ms=0, flags=0, stall_rounds=0, device=0):
+        o = mf_batch_default_opts()
+        o.device = device
+        o.time_budget_ms = time_budget_ms
+        o.use_graph = 1 if use_graph else 0
+        o.flags = flags
+        o.stall_rounds = stall_rounds
+        if n_classes is not None:
+            o.n_classes = n_classes
+        for name, val in (("class_max_arcs", class_max_arcs), ("block", block), ("kernel_cycles", kernel_cycles)):
+            if val is not None:
+                arr = getattr(o, name)
+                for i, x in enumerate(val):
+                    arr[i] = x
+        self.ns = [int(g.n) for g in graphs]
+        self.b = mf_batch_create(graphs, caps, o)
+
+    def close(self):
+        if self.b:
+            mf_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def solve(self) -> np.ndarray:
+        mf_batch_solve(self.b)
+        return mf_batch_values(self.b)
+
+    def values(self) -> np.ndarray:
+        return mf_batch_values(self.b)
+
+    def solve_class(self, cls: int) -> float:
+        return mf_batch_solve_class(self.b, cls)
+
+    def autotune(self, repeats: int = 3) -> dict:
+        return mf_batch_autotune(self.b, repeats).as_dict()
+
+    def opts(self) -> dict:
+        return mf_batch_get_opts(self.b).as_dict()
+
+    def set_opts(self, **kw):
+        o = mf_batch_get_opts(self.b)
+        for k, v in kw.items():
+            if hasattr(v, "__len__"):
+                arr = getattr(o, k)
+                for i, x in enumerate(v):
+                    arr[i] = x
+            else:
+                setattr(o, k, v)
+        mf_batch_set_opts(self.b, o)
+
+    def last_ms(self) -> float:
+        return mf_batch_last_ms(self.b)
+
+    def num_arcs(self) -> np.ndarray:
+        return mf_batch_num_arcs(self.b)
+
+    def min_cut(self, i: int):
+        # an out-of-range index is rejected by the library (MF_EINVAL)
+        return mf_batch_min_cut(self.b, i, self.ns[i] if 0 <= i < len(self.ns) else 0)
+
+    def stats(self, i: int) -> dict:
+        return mf_batch_get_stats(self.b, i)
+
+    def set_capacities(self, i: int, edge_ids, new_caps):
+        mf_batch_set_capacities(self.b, i, edge_ids, new_caps)
 
 
 # Load at import: a missing or broken library is an ImportError, never a fallback.
