@@ -52,6 +52,8 @@ CONFIGS = {
                      inc_hi=100),
     "c4": dict(desc="256 uneven instances (grids 32^2..256^2, random graphs 1k..50k V at degree 8), "
                     "batched static solve"),
+    "c5": dict(desc="R-MAT scale 22 (4,194,304 V / 67,108,864 E) served: requests of 10..100k edges "
+                    "(log-uniform), Poisson arrivals"),
 }
 
 
@@ -232,6 +234,96 @@ def run_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def run_serving(args):
+    """C5: one resident R-MAT scale-22 graph behind the serving runtime.
+    A closed loop (submit, wait) over the first requests calibrates the mean
+    service time S; then two open-loop phases submit Poisson arrivals at rate
+    rho/S for rho = 0.5 and 0.8, and report arrival-to-result latency and
+    update throughput.  The final value is checked against a static solve of
+    the final capacities on a second handle."""
+    import threading
+    import torch
+    import workloads as W
+    from paper_2511_05895_amd import mf
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    t0 = time.perf_counter()
+    g = W.c5_rmat22()
+    print(f"[bench] c5 graph generated in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    nc, no = args.closed_requests, args.open_requests
+    reqs = list(W.request_stream(g, nc + 2 * no, W.SEED_BASE + 4))
+    S = mf.Server(workers=args.workers)
+    t0 = time.perf_counter()
+    gid, v0 = S.add_graph(g)
+    print(f"[bench] admitted and solved in {time.perf_counter() - t0:.1f} s (value {v0})",
+          file=sys.stderr, flush=True)
+    closed = []
+    for j in range(nc):
+        r = S.wait(S.submit(gid, *reqs[j]))
+        closed.append(r)
+    service = float(np.mean([r["done_ms"] - r["start_ms"] for r in closed]))
+    print(f"[bench] closed loop: mean service {service:.1f} ms", file=sys.stderr, flush=True)
+    phases = {}
+    nxt = nc
+    for rho in (0.5, 0.8):
+        rate = rho / (service * 1e-3)  # arrivals per second
+        rng = np.random.default_rng(int(rho * 10))
+        gaps = rng.exponential(1.0 / rate, no)
+        rids = []
+        start = time.perf_counter()
+        t_arr = start
+        for j in range(no):
+            t_arr += gaps[j]
+            delay = t_arr - time.perf_counter()
+            if delay > 0:
+                time.sleep(delay)
+            rids.append((S.submit(gid, *reqs[nxt + j]), int(reqs[nxt + j][0].shape[0])))
+        res = [S.wait(r) for r, _ in rids]
+        span = time.perf_counter() - start
+        nxt += no
+        lat = np.array([r["done_ms"] - r["submit_ms"] for r in res])
+        edges = sum(k for _, k in rids)
+        phases[rho] = {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                       "update_edges_per_s": edges / span, "requests": no,
+                       "commits": len({(r["start_ms"], r["done_ms"]) for r in res}),
+                       "mean_group": float(np.mean([r["group_size"] for r in res]))}
+        print(f"[bench] rho {rho}: p50 {phases[rho]['p50_ms']:.1f} ms, p99 {phases[rho]['p99_ms']:.1f} ms",
+              file=sys.stderr, flush=True)
+    version, value = S.graph_info(gid)
+    S.close()
+    # final value against a static solve of the final capacities
+    cap = g.cap.copy()
+    for ids, new in reqs:
+        cap[ids] = new
+    with mf.MaxFlow(g, cap=cap) as F:
+        A = F.num_arcs
+        t0 = time.perf_counter()
+        static_value = F.solve()
+        static_ms = (time.perf_counter() - t0) * 1e3
+    if version != len(reqs) or static_value != value:
+        raise SystemExit(f"FAIL: served value {value} at version {version} != static {static_value}")
+    svc = np.array([r["done_ms"] - r["start_ms"] for r in closed])
+    hi = phases[0.8]
+    out = {
+        "metric": "serving: arrival-to-result latency p50/p99 and update edges/s at load 0.8, exact flow",
+        "value": hi["update_edges_per_s"],
+        "unit": "update edges/s (served, load 0.8)",
+        "n_gpus": 1, "steps": 2 * no, "warmup": nc,
+        "ms_per_step": float(np.mean(svc)),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "int32 capacities / int64 excess", "data": "synthetic (seeded generator)",
+        "config": {"workload": CONFIGS["c5"]["desc"], "n": g.n, "m": g.m, "arcs": A,
+                   "workers": args.workers, "closed_requests": nc, "open_requests_per_load": no},
+        "closed_loop_service_ms": {"mean": float(svc.mean()), "p50": float(np.percentile(svc, 50)),
+                                   "p99": float(np.percentile(svc, 99))},
+        "load_0.5": phases[0.5], "load_0.8": hi,
+        "residual_edges_per_s_closed": A / (svc.mean() * 1e-3),
+        "static_solve_ms": static_ms,
+        "exact": f"final served value == static solve of the final capacities ({value})",
+    }
+    print(json.dumps(out), flush=True)
+
+
 def summarize_profile(path):
     """Per-kernel duration table from a rocprofv3 kernel-trace output: the
     rocpd SQLite database or the kernel_trace CSV."""
@@ -326,6 +418,9 @@ def main():
     ap.add_argument("--grid-blocks", type=int, default=16)
     ap.add_argument("--kernel-cycles", type=int, default=1)
     ap.add_argument("--mode", type=int, default=0)
+    ap.add_argument("--workers", type=int, default=2, help="serving workers (c5)")
+    ap.add_argument("--closed-requests", type=int, default=30, help="closed-loop requests (c5)")
+    ap.add_argument("--open-requests", type=int, default=100, help="open-loop requests per load (c5)")
     ap.add_argument("--calibration-copy-mib", type=int, default=0,
                     help="run a float32 negate over this many MiB first (HBM counter calibration)")
     args = ap.parse_args()
@@ -335,6 +430,9 @@ def main():
         sys.exit(2)
     if args.config == "c4":
         run_batch(args)
+        return
+    if args.config == "c5":
+        run_serving(args)
         return
 
     import torch

@@ -40,6 +40,7 @@ extern "C" {
 #define MF_EDEVICE 3  /* HIP runtime error or device-side abort              */
 #define MF_ESTATE 4   /* call not allowed in the handle's current state      */
 #define MF_ETIMEOUT 5 /* iteration limit reached before the loop converged   */
+#define MF_EPENDING 6 /* (server) the request has not been committed yet     */
 
 /* work distribution of the push/relabel and invalid-edge sweeps */
 #define MF_MODE_DATA 0     /* worklist of active vertices (Sec. 5.3)          */
@@ -207,6 +208,11 @@ MF_API int mf_get_stats(const mf_handle_t *h, mf_stats_t *out);
  * capacity an edge may take, min(2^30, (2^31-1) / (2k)) for k the largest
  * number of input edges between one vertex pair, so that an arc's residual
  * stays inside int32 even after one batch of deltas lands before the clamp. */
+/* Upper bound of the device bytes one handle of a graph with n vertices and
+ * m edges allocates (merged arcs bounded by 2m), staging of update batches
+ * excluded; -1 for negative sizes.  Used for admission by the server. */
+MF_API int64_t mf_estimate_device_bytes(int32_t n, int64_t m);
+
 MF_API int mf_num_arcs(const mf_handle_t *h, int32_t *A_out);
 MF_API int mf_cap_limit(const mf_handle_t *h, int32_t *limit_out);
 
@@ -325,6 +331,163 @@ MF_API int mf_batch_get_stats(mf_batch_t *b, int32_t i, mf_stats_t *stats);
  * solve uses them.  A rejected batch (MF_EINVAL) changes nothing. */
 MF_API int mf_batch_set_capacities(mf_batch_t *b, int32_t i, const int64_t *edge_ids,
                                    const int32_t *new_caps, int64_t k);
+
+/* ------------------------------------------------------------------------
+ * Learned phase schedule.
+ *
+ * The paper sets how long push/relabel runs between two global relabels
+ * with one fixed knob (KERNELCYCLES, Sec. 6: too few cycles cost extra
+ * global relabels, too many push in the wrong direction).  Here each phase
+ * (the work between two global relabels) may take one of MF_POLICY_ACTIONS
+ * limit settings, chosen right after the global relabel that opens it:
+ *   action:                 0    1    2    3    4    5    6    7
+ *   relabel budget x        1  1/4  1/2    2    4    1    1    1
+ *   rounds per BFS level x  1    1    1    1    2  1/2    2    1
+ *   stall limit x           1    1    1    1    1    1  1/2  none
+ * Action 0 is the fixed rule of mf_opts_t.  Every action keeps the results
+ * exact (only the moment of the next global relabel changes).
+ *
+ * The choice is made by a value network q = W3 relu(W2 relu(W1 x + b1) + b2)
+ * + b3 (fp32; MF_POLICY_FEATURES inputs, MF_POLICY_HIDDEN units per hidden
+ * layer, one output per action) that predicts, for each action, the log of
+ * the remaining solve time in ms.  The features x of a phase, computed on
+ * the device right after its global relabel:
+ *   x0  log2(1 + active vertices) / 24
+ *   x1  log2(1 + sum of their excess) / 40
+ *   x2..x9  fraction of them with floor(log2 e) / 4 = 0, 1, ..., 6, >= 7
+ *   x10 log2(1 + BFS levels) / 12
+ *   x11 fraction of the vertices the BFS reached (h < |V|)
+ *   x12 log2(1 + pushes of the previous phase of the call) / 32
+ *   x13 log2(1 + relabels of the previous phase) / 32
+ *   x14 log2(1 + phase index in the call) / 8
+ *   x15 edges of the update batch / m (1 for a static solve)
+ * Parameters: one flat fp32 vector, W1 (H x F, row-major), b1, W2 (H x H),
+ * b2, W3 (K x H), b3.  Training (mf_policy_train) runs full-batch Adam on the
+ * device over samples (x, taken action a, target y), minimising
+ * (1/N) sum (q[a] - y)^2.
+ * ------------------------------------------------------------------------ */
+#define MF_POLICY_FEATURES 16
+#define MF_POLICY_HIDDEN 32
+#define MF_POLICY_ACTIONS 8
+#define MF_POLICY_FIXED 0    /* action 0 always; no network, no features      */
+#define MF_POLICY_LEARNED 1  /* argmin of q when it beats q[0] by the margin,
+                                else action 0 (the fixed rule is the fallback) */
+#define MF_POLICY_EXPLORE 2  /* a uniformly drawn action with probability
+                                `explore`, else action 0 (training data)       */
+#define MF_POLICY_FORCED 3   /* `action` in every phase                        */
+
+typedef struct mf_policy mf_policy_t;
+
+MF_API const char *mf_policy_last_error(void);
+MF_API int32_t mf_policy_num_params(void);
+/* Network on `device` with He-initialised weights drawn from `seed`
+ * (splitmix64 counters, Box-Muller), zero biases. */
+MF_API int mf_policy_create(int32_t device, uint64_t seed, mf_policy_t **out);
+MF_API void mf_policy_destroy(mf_policy_t *p);
+MF_API int mf_policy_get_params(mf_policy_t *p, float *out);
+/* Also resets the Adam moments. */
+MF_API int mf_policy_set_params(mf_policy_t *p, const float *in);
+/* Q (host, N x MF_POLICY_ACTIONS) for features X (host, N x
+ * MF_POLICY_FEATURES), computed on the device. */
+MF_API int mf_policy_forward(mf_policy_t *p, const float *X, int32_t N, float *Q);
+/* Loss and its gradient (host, mf_policy_num_params() floats) at the current
+ * parameters; nothing is updated. */
+MF_API int mf_policy_gradient(mf_policy_t *p, const float *X, const int32_t *actions, const float *targets,
+                              int32_t N, float *grad, float *loss);
+/* `steps` full-batch Adam steps (lr; beta 0.9 / 0.999; eps 1e-8) on the
+ * device; *final_loss (may be NULL) is the loss after the last step. */
+MF_API int mf_policy_train(mf_policy_t *p, const float *X, const int32_t *actions, const float *targets,
+                           int32_t N, int32_t steps, float lr, float *final_loss);
+/* Schedule of a handle's later solving calls.  The policy object must
+ * outlive its use by the handle.  margin >= 0 (learned), explore in [0, 1]
+ * and seed (explore), action (forced). */
+MF_API int mf_set_policy(mf_handle_t *h, const mf_policy_t *policy, int32_t mode, float margin, float explore,
+                         uint64_t seed, int32_t action);
+/* Per-phase records of the last solving call under a non-fixed mode:
+ * MF_POLICY_FEATURES + 2 floats each (features, action taken, phase
+ * duration in ms); copies min(recorded, max_phases); *n_out = recorded. */
+MF_API int mf_get_policy_trace(mf_handle_t *h, float *out, int32_t max_phases, int32_t *n_out);
+
+/* ------------------------------------------------------------------------
+ * Serving runtime: resident graphs taking asynchronous update requests.
+ *
+ * Each graph admitted to a server keeps its handle (and its solved state)
+ * on the device.  A request is one update batch of one graph (absolute new
+ * capacities of distinct edges, Sec. 4.1); it is validated and copied on
+ * submit and queued FIFO behind the graph's earlier requests.  Worker threads
+ * take ALL pending requests of a graph (up to max_group_requests and
+ * max_group_edges) and commit them together: the requests are merged into one
+ * set in which the latest request wins for an edge -- since capacities are
+ * absolute this equals applying them one after the other -- and one dynamic
+ * repair (Alg. 4/5) runs for the group.  Every request of the group then
+ * receives the flow value after that commit and the graph's version, the
+ * number of its requests applied so far (at least the request's own sequence
+ * number): the value equals the maximum flow of the graph after its first
+ * `version` requests.  Different graphs are committed by different workers at
+ * the same time on their own streams.  Admission: a graph is accepted only
+ * while the device bytes reserved for all resident graphs
+ * (mf_estimate_device_bytes + staging for max_group_edges updates) stay within
+ * memory_budget; otherwise MF_ENOMEM and nothing changes.
+ * All mf_server_* calls are thread-safe; errors are reported per thread by
+ * mf_server_last_error().
+ * ------------------------------------------------------------------------ */
+typedef struct mf_server mf_server_t;
+
+typedef struct {
+    int32_t device;
+    int32_t workers;            /* threads committing groups (default 4)      */
+    int64_t memory_budget;      /* device bytes for resident graphs; 0 = 90 %
+                                   of the free device memory at creation     */
+    int64_t max_group_edges;    /* edges one commit may merge (default 2^20;
+                                   a larger single request is still taken)   */
+    int32_t max_group_requests; /* requests one commit may merge (default 64; 1
+                                   = no group commit)                         */
+    int32_t reserved[3];        /* must be zero                               */
+} mf_server_opts_t;
+
+typedef struct {
+    int32_t status;      /* MF_OK, or the error of the commit (MF_ESTATE after
+                            an earlier commit of the graph failed)          */
+    int32_t graph;
+    int64_t request;
+    int64_t value;       /* flow value after the commit                     */
+    int64_t version;     /* requests of the graph applied by then           */
+    int64_t seq;         /* this request's 1-based sequence number in its graph */
+    int64_t group_size;  /* requests merged into the commit                 */
+    double submit_ms;    /* server clock (ms since creation): submitted,    */
+    double start_ms;     /* commit started,                                  */
+    double done_ms;      /* result available                                 */
+} mf_result_t;
+
+MF_API void mf_server_default_opts(mf_server_opts_t *opts);
+MF_API const char *mf_server_last_error(void);
+MF_API int mf_server_create(const mf_server_opts_t *opts, mf_server_t **out);
+/* Waits until every submitted request is committed, then frees everything. */
+MF_API void mf_server_destroy(mf_server_t *s);
+/* Admit a graph (arguments as mf_create; opts->device is the server's),
+ * solve it statically; *graph_id and *value (may be NULL) receive its id and
+ * initial flow value. */
+MF_API int mf_server_add_graph(mf_server_t *s, const mf_csr_t *g, const int32_t *cap, int32_t src, int32_t sink,
+                               const mf_opts_t *opts, int32_t *graph_id, int64_t *value);
+/* Stop taking requests for the graph, wait for its queue, free its handle
+ * and its reservation. */
+MF_API int mf_server_remove_graph(mf_server_t *s, int32_t graph_id);
+/* Queue one request; returns at once with *request_id.  MF_EINVAL (nothing
+ * queued) for an unknown graph, an id outside [0, m), a capacity outside the
+ * graph's per-edge limit, or a repeated id. */
+MF_API int mf_server_submit(mf_server_t *s, int32_t graph_id, const int64_t *edge_ids, const int32_t *new_caps,
+                            int64_t k, int64_t *request_id);
+/* MF_OK with *out filled once the request is committed; MF_EPENDING before. */
+MF_API int mf_server_poll(mf_server_t *s, int64_t request_id, mf_result_t *out);
+/* Block until the request is committed. */
+MF_API int mf_server_wait(mf_server_t *s, int64_t request_id, mf_result_t *out);
+/* Block until every submitted request is committed. */
+MF_API int mf_server_drain(mf_server_t *s);
+/* Version and flow value of the graph's last commit. */
+MF_API int mf_server_graph_info(mf_server_t *s, int32_t graph_id, int64_t *version, int64_t *value);
+/* Reserved device bytes, the budget and the number of commits so far (any
+ * pointer may be NULL). */
+MF_API int mf_server_memory(mf_server_t *s, int64_t *reserved, int64_t *budget, int64_t *commits);
 
 #ifdef __cplusplus
 }

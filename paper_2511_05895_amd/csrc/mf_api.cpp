@@ -49,6 +49,15 @@ struct mf_handle {
     int32_t stall_rounds = 3;
     double tick_ms = 1e-5;  // one wall-clock tick in ms
     int32_t seq = 1;  // next round id; round ids stamp mark[] and rmark[]
+    // learned phase schedule (mf_set_policy)
+    const mf_policy_t *policy = nullptr;
+    int32_t policy_mode = MF_POLICY_FIXED;
+    float policy_margin = 0.f;
+    float policy_explore = 0.f;
+    uint64_t policy_seed = 0;
+    int32_t policy_action = 0;
+    float *d_ptrace = nullptr;
+    float batch_fraction = 1.f;  // of the current call
     int32_t epoch = 0;
     State state = State::NoFlow;
     int64_t value = 0;
@@ -94,6 +103,7 @@ void release(mf_handle_t *h) {
     h->allocs.clear();
     if (h->d_ids) (void)hipFree(h->d_ids);
     if (h->d_caps) (void)hipFree(h->d_caps);
+    if (h->d_ptrace) (void)hipFree(h->d_ptrace);
     if (h->h_ctrl) (void)hipHostFree(h->h_ctrl);
     for (auto &e : h->ev)
         if (e) (void)hipEventDestroy(e);
@@ -128,9 +138,25 @@ int run_loop_and_finish(mf_handle_t *h) {
         HIP_TRY(h, mf::launch_fill_i32(h->g.rmark, h->g.n, 0, h->stream));
         h->seq = 1;
     }
-    mf::LoopParams p{h->kc, h->mode, h->max_iter, h->deadline_ticks, h->barrier_ticks,
-                     h->relabel_budget, h->max_rounds, h->seq, h->rounds_per_level, h->use_gap,
-                     h->stall_rounds, 0};
+    mf::LoopParams p{};
+    p.kc = h->kc;
+    p.mode = h->mode;
+    p.max_iter = h->max_iter;
+    p.deadline_ticks = h->deadline_ticks;
+    p.barrier_ticks = h->barrier_ticks;
+    p.relabel_budget = h->relabel_budget;
+    p.max_rounds = h->max_rounds;
+    p.seq_base = h->seq;
+    p.rounds_per_level = h->rounds_per_level;
+    p.use_gap = h->use_gap;
+    p.stall_rounds = h->stall_rounds;
+    p.policy_mode = h->policy_mode;
+    p.policy_w = mf::policy_device_params(h->policy);
+    p.policy_margin = h->policy_margin;
+    p.policy_explore = h->policy_explore;
+    p.policy_seed = h->policy_seed;
+    p.policy_action = h->policy_action;
+    p.batch_fraction = h->batch_fraction;
     // height counts of the gap heuristic start at zero (the loop clears them
     // again before every later global relabel)
     HIP_TRY(h, mf::launch_fill_i32(h->g.hcount, (int64_t)h->g.n + 1, 0, h->stream));
@@ -209,6 +235,7 @@ int apply_device(mf_handle_t *h, const int64_t *d_ids, const int32_t *d_caps, in
     HIP_TRY(h, mf::launch_apply_delta(h->g, d_ids, d_caps, k, h->stream));
     HIP_TRY(h, mf::launch_clamp(h->g, d_ids, k, h->stream));
     HIP_TRY(h, mf::launch_saturate_source(h->g, h->stream));
+    h->batch_fraction = h->g.m > 0 ? (float)((double)k / (double)h->g.m) : 0.f;
     rc = run_loop_and_finish(h);
     if (rc == MF_EINVAL) return update_error_text(h, h->h_ctrl->err);
     return rc;
@@ -411,6 +438,7 @@ MF_API int mf_solve(mf_handle_t *h) {
     HIP_TRY(h, mf::launch_init_state(h->g, h->stream));
     HIP_TRY(h, mf::launch_saturate_source(h->g, h->stream));
     h->state = State::Partial;
+    h->batch_fraction = 1.f;
     return run_loop_and_finish(h);
 }
 
@@ -498,6 +526,25 @@ MF_API int mf_get_stats(const mf_handle_t *h, mf_stats_t *out) {
     return MF_OK;
 }
 
+MF_API int64_t mf_estimate_device_bytes(int32_t n, int64_t m) {
+    if (n < 0 || m < 0) return -1;
+    const int64_t A = 2 * m;  // upper bound before merging
+    const int64_t qcap = (int64_t)n + A / mf::kChunk + 64;
+    int64_t b = 0;
+    b += 4 * ((int64_t)n + 1);            // row_ptr
+    b += (8 + 4 + 4) * A;                 // arc, twin, cap
+    b += (4 + 4 + 4) * m;                 // edge2arc, ecap, stamp
+    b += (8 + 4) * (int64_t)n;            // e, h
+    b += 2 * 8 * qcap;                    // frontier items
+    b += (3 + 3) * 4 * (int64_t)n;        // lists, mark, rmark, relab
+    b += 4 * ((int64_t)n + 1);            // hcount
+    b += 4 * (int64_t)n;                  // heavy vertices (at most n)
+    b += (int64_t)n;                      // cut side
+    b += (int64_t)sizeof(mf::Ctrl);
+    b += 256 * 24;                        // allocation rounding of the ~24 arrays
+    return b;
+}
+
 MF_API int mf_num_arcs(const mf_handle_t *h, int32_t *A_out) {
     if (!h || !A_out) return fail(const_cast<mf_handle_t *>(h), MF_EINVAL, "null argument");
     *A_out = h->g.A;
@@ -557,6 +604,52 @@ MF_API int mf_get_trace(const mf_handle_t *h, int32_t *out, int32_t max_phases, 
     const int32_t nrec = std::min<int32_t>(c.ntrace, mf::kTraceCap);
     const int32_t k = std::min(nrec, max_phases);
     if (k > 0) std::memcpy(out, c.trace, sizeof(int32_t) * mf::kTraceFields * k);
+    if (n_out) *n_out = nrec;
+    return MF_OK;
+}
+
+MF_API int mf_set_policy(mf_handle_t *h, const mf_policy_t *policy, int32_t mode, float margin, float explore,
+                         uint64_t seed, int32_t action) {
+    if (!h) return fail(nullptr, MF_EINVAL, "null handle");
+    if (mode < MF_POLICY_FIXED || mode > MF_POLICY_FORCED) return fail(h, MF_EINVAL, "unknown policy mode");
+    if (mode == MF_POLICY_LEARNED && !policy) return fail(h, MF_EINVAL, "the learned mode needs a policy");
+    if (policy && mf::policy_device(policy) != h->device)
+        return fail(h, MF_EINVAL, "the policy lives on another device");
+    if (!(margin >= 0.f) || !(explore >= 0.f && explore <= 1.f))
+        return fail(h, MF_EINVAL, "margin must be >= 0 and explore in [0, 1]");
+    if (mode == MF_POLICY_FORCED && (action < 0 || action >= MF_POLICY_ACTIONS))
+        return fail(h, MF_EINVAL, "action out of range");
+    if (mode != MF_POLICY_FIXED && !h->d_ptrace) {
+        HIP_TRY(h, hipSetDevice(h->device));
+        HIP_TRY(h, hipStreamSynchronize(h->stream));
+        void *q = nullptr;
+        if (hipMalloc(&q, sizeof(float) * mf::kTraceCap * mf::kPolRec) != hipSuccess)
+            return fail(h, MF_ENOMEM, "cannot allocate the policy trace");
+        h->d_ptrace = static_cast<float *>(q);
+        h->g.ptrace = h->d_ptrace;
+    }
+    h->policy = policy;
+    h->policy_mode = mode;
+    h->policy_margin = margin;
+    h->policy_explore = explore;
+    h->policy_seed = seed;
+    h->policy_action = action;
+    return MF_OK;
+}
+
+MF_API int mf_get_policy_trace(mf_handle_t *h, float *out, int32_t max_phases, int32_t *n_out) {
+    if (!h || (max_phases > 0 && !out) || max_phases < 0) return fail(h, MF_EINVAL, "bad trace arguments");
+    const int32_t nrec = h->d_ptrace && h->policy_mode != MF_POLICY_FIXED
+                             ? std::min<int32_t>(h->h_ctrl->ntrace, mf::kTraceCap)
+                             : 0;
+    const int32_t k = std::min(nrec, max_phases);
+    if (k > 0) {
+        HIP_TRY(h, hipSetDevice(h->device));
+        HIP_TRY(h, hipMemcpyAsync(out, h->d_ptrace, sizeof(float) * mf::kPolRec * k, hipMemcpyDeviceToHost,
+                                  h->stream));
+        HIP_TRY(h, hipStreamSynchronize(h->stream));
+        for (int32_t i = 0; i < k; ++i) out[(int64_t)i * mf::kPolRec + mf::kPolF + 1] *= (float)h->tick_ms;
+    }
     if (n_out) *n_out = nrec;
     return MF_OK;
 }

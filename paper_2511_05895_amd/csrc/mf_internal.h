@@ -32,6 +32,16 @@ enum : int {
     kTrLastDeliv     // last round in which excess reached t or a deficient vertex
 };
 
+// Learned phase schedule: sizes of the value network (features, hidden
+// units, actions), its flat parameter count, and one policy-trace record per
+// phase (features, action, phase duration in wall-clock ticks).
+constexpr int kPolF = 16;
+constexpr int kPolH = 32;
+constexpr int kPolK = 8;
+constexpr int kPolParams = kPolH * kPolF + kPolH + kPolH * kPolH + kPolH + kPolK * kPolH + kPolK;
+constexpr int kPolRec = kPolF + 2;
+enum : int32_t { kPolicyFixed = 0, kPolicyLearned = 1, kPolicyExplore = 2, kPolicyForced = 3 };
+
 // Loop status written by the persistent kernel.
 enum : int32_t { kRunning = 0, kSolved = 1, kIterLimit = 2, kAborted = 3, kDeadline = 4 };
 
@@ -92,6 +102,12 @@ struct Ctrl {
     int64_t phase_deliv;     // excess delivered into t or deficient vertices this phase
     int32_t ntrace;          // phases recorded in trace[]
     int32_t gap;             // lowest height found empty in this phase (|V| = none)
+    int64_t feat_esum;       // excess of the active vertices found by this phase's BFS
+    int32_t feat_hist[8];    // their count per bin of floor(log2 e) / 4 (last bin open)
+    int32_t action;          // phase action chosen by the schedule
+    int32_t pad2_;
+    int64_t prev_pushes;     // pushes and relabels of the previous phase of the call
+    int64_t prev_relabels;
     int32_t trace[kTraceCap][kTraceFields];
     int64_t deficit;    // sum of e(v) < 0 over v not in {s, t} at termination
     int64_t e_t;        // e(t) at termination
@@ -122,6 +138,7 @@ struct DevGraph {
     int32_t *hcount;    // n+1: vertices at each height below |V| (gap heuristic)
     int32_t *heavy_all; // vertices with long arc lists (topology-driven sweeps)
     int32_t n_heavy_all;
+    float *ptrace;      // kTraceCap x kPolRec policy-trace records, or null
     Ctrl *ctrl;
 };
 
@@ -138,7 +155,13 @@ struct LoopParams {
                                // level of the BFS that started it (+16)
     int32_t use_gap;           // gap heuristic on (1) or off (0)
     int32_t stall_rounds;      // > 0: a phase ends after max(this, BFS levels) rounds without delivery
-    int32_t pad_;
+    int32_t policy_mode;       // kPolicyFixed / Learned / Explore / Forced
+    const float *policy_w;     // value-network parameters (kPolParams), or null
+    float policy_margin;       // learned: leave action 0 only when it predicts this much less
+    float policy_explore;      // explore: probability of a uniformly drawn action
+    uint64_t policy_seed;      // explore: counter-based draws keyed by (seed, seq_base, phase)
+    int32_t policy_action;     // forced: the action of every phase
+    float batch_fraction;      // edges of the update batch / m (1 for a static solve)
 };
 
 // Result of one instance of a batched solve.
@@ -165,7 +188,21 @@ hipError_t launch_min_cut(const DevGraph &g, uint8_t *d_side, hipStream_t st);
 hipError_t launch_batch(const DevGraph *graphs, const int32_t *order, int count, const LoopParams &p,
                         const int32_t *kc, BatchResult *res, int block, hipStream_t st);
 hipError_t launch_fill_i32(int32_t *p, int64_t count, int32_t value, hipStream_t st);
+hipError_t launch_fill_f32(float *p, int64_t count, float value, hipStream_t st);
+// Value network (mf_policy.hip): loss gradient over N samples (grad and loss
+// are cleared first), forward outputs, one Adam step.
+hipError_t launch_mlp_grad(const float *theta, const float *X, const int32_t *act, const float *y, int N,
+                           float *grad, float *loss, hipStream_t st);
+hipError_t launch_mlp_forward(const float *theta, const float *X, int N, float *Q, hipStream_t st);
+hipError_t launch_adam(float *theta, const float *grad, float *m, float *v, int step, float lr, hipStream_t st);
 // Largest co-resident workgroup count of the loop kernel.
 hipError_t loop_max_coresident(int device, int *blocks);
 
+}  // namespace mf
+
+struct mf_policy;
+namespace mf {
+// Device parameters and device of a policy object (mf_policy_api.cpp).
+const float *policy_device_params(const mf_policy *p);
+int policy_device(const mf_policy *p);
 }  // namespace mf

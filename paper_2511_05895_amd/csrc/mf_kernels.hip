@@ -140,6 +140,15 @@ __device__ __forceinline__ int wave_appendn(int32_t *counter, int c) {
 
 __device__ __forceinline__ int n_items(int deg) { return (deg + kChunk - 1) / kChunk; }
 
+// A value every lane of the wavefront holds alike (read after a barrier),
+// moved to a scalar register so it does not occupy a vector register.
+__device__ __forceinline__ int32_t uniform(int32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ int64_t uniform(int64_t x) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(uint32_t)x);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(uint32_t)((uint64_t)x >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 // The workgroups that run one solve loop together: ranks 0..size-1.  Either
 // the whole grid of a cooperative launch, or a single workgroup of a batched
 // launch (then every barrier is a workgroup barrier).
@@ -254,13 +263,28 @@ __device__ void bfs_roots(const DevGraph &g, const Team &tm, Tally &tl) {
     }
 }
 
+// Features of the learned schedule: excess sum of the active vertices a BFS
+// finds and their count per bin of floor(log2 e) / 4.  Wave-uniform calls.
+template <int SC>
+__device__ __forceinline__ void feature_tally(Ctrl *c, bool active, int64_t ev) {
+    if (__ballot(active) == 0) return;
+    const int64_t es = wave_sum(active ? ev : (int64_t)0);
+    const int bin = active ? min(7, (63 - __clzll((unsigned long long)ev)) >> 2) : -1;
+    if (lane_id() == 0) add<SC>(&c->feat_esum, es);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+        const int cb = __popcll(__ballot(bin == b));
+        if (lane_id() == 0 && cb) add<SC>(&c->feat_hist[b], cb);
+    }
+}
+
 // One BFS level, top-down: for every arc (w -> v) of a frontier item, v joins
 // level L+1 when it is unvisited (height |V|), is not s, and has residual
 // capacity toward w (the twin arc v -> w).  Newly reached vertices become
 // frontier items of the next level; those with positive excess go to the
 // active worklist (A of Alg. 1: e > 0 and h < |V|, s and t excluded).
 template <int SC>
-__device__ void bfs_level(const DevGraph &g, const Team &tm, int L, Tally &tl) {
+__device__ void bfs_level(const DevGraph &g, const Team &tm, int L, bool feats, Tally &tl) {
     const int2 *__restrict__ qin = g.q[L & 1];
     int2 *qout = g.q[(L + 1) & 1];
     const int cnt = ld<SC>(&g.ctrl->qcount[L % 3]);
@@ -308,12 +332,15 @@ __device__ void bfs_level(const DevGraph &g, const Team &tm, int L, Tally &tl) {
             }
             int vbeg = 0, vend = 0;
             bool active = false;
+            int64_t ev = 0;
             if (disc) {
                 vbeg = g.row_ptr[v];
                 vend = g.row_ptr[v + 1];
-                active = (v != g.t) && g.e[v] > 0;
+                ev = g.e[v];
+                active = (v != g.t) && ev > 0;
                 tl.bfs_v++;
             }
+            if (feats) feature_tally<SC>(g.ctrl, active, ev);
             const int vdeg = vend - vbeg;
             const int ndisc = __popcll(__ballot(disc));
             if (lane_id() == 0 && ndisc) add<SC>(&g.hcount[L + 1], ndisc);
@@ -682,6 +709,103 @@ __device__ void remove_invalid(const DevGraph &g, const Team &tm, const int32_t 
 }
 
 // ---------------------------------------------------------------------------
+// Learned phase schedule
+//
+// Right after a global relabel found active vertices, the schedule picks the
+// limits of the coming phase among kPolK actions: relabel budget x b/4,
+// rounds per BFS level x r/2, stall limit x l/2 (0: none).  Action 0 is the
+// fixed rule.  Every action keeps the result exact: only the moment of the
+// next global relabel changes.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ int act_budget(int a) { return a == 1 ? 1 : a == 2 ? 2 : a == 3 ? 8 : a == 4 ? 16 : 4; }
+__device__ __forceinline__ int act_rpl(int a) { return a == 4 || a == 6 ? 4 : a == 5 ? 1 : 2; }
+__device__ __forceinline__ int act_stall(int a) { return a == 6 ? 1 : a == 7 ? 0 : 2; }
+
+// splitmix64 finaliser (Steele, Lea and Flood, 2014): counter-based draws of
+// the exploration mode.
+__device__ __forceinline__ uint64_t mix64(uint64_t x) {
+    x += 0x9E3779B97F4A7C15ull;
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+    return x ^ (x >> 31);
+}
+
+// Run by the 64 lanes of the leader's wavefront after the barrier that ends
+// the BFS.  Features (every lane computes them), then the action: the
+// network's lowest predicted cost
+// when it beats action 0 by the margin (learned), a seeded draw (explore) or
+// a fixed action (forced).  Lane 0 publishes the action in Ctrl; the features
+// and the action go to the policy trace.
+template <int SC>
+__device__ int policy_decide(const DevGraph &g, const LoopParams &p, Ctrl *c, int L, int64_t iter) {
+    constexpr int F = kPolF, H = kPolH, K = kPolK;
+    constexpr int oW1 = 0, ob1 = oW1 + H * F, oW2 = ob1 + H, ob2 = oW2 + H * H, oW3 = ob2 + H, ob3 = oW3 + K * H;
+    const int lane = lane_id();
+    int64_t reached = 0;
+    for (int l = lane; l <= L; l += 64) reached += ld<SC>(&g.hcount[l]);
+    reached = wave_sum(reached);
+    const int cnt = ld<SC>(&c->lst[0].light) + ld<SC>(&c->lst[0].heavy);
+    const int64_t es = ld<SC>(&c->feat_esum);
+    float x[F];
+    x[0] = log2f((float)(1 + cnt)) / 24.f;
+    x[1] = log2f((float)(1 + es)) / 40.f;
+#pragma unroll
+    for (int b = 0; b < 8; ++b) x[2 + b] = cnt ? (float)ld<SC>(&c->feat_hist[b]) / (float)cnt : 0.f;
+    x[10] = log2f((float)(1 + L)) / 12.f;
+    x[11] = (float)reached / (float)g.n;
+    x[12] = log2f((float)(1 + ld<SC>(&c->prev_pushes))) / 32.f;
+    x[13] = log2f((float)(1 + ld<SC>(&c->prev_relabels))) / 32.f;
+    x[14] = log2f((float)(1 + iter)) / 8.f;
+    x[15] = p.batch_fraction;
+    int act = 0;
+    if (p.policy_mode == kPolicyLearned) {
+        const float *W = p.policy_w;
+        const int j = lane & (H - 1);
+        float z = W[ob1 + j];
+#pragma unroll
+        for (int i = 0; i < F; ++i) z = fmaf(W[oW1 + j * F + i], x[i], z);
+        const float h1 = z > 0.f ? z : 0.f;
+        float z2 = W[ob2 + j];
+#pragma unroll
+        for (int l = 0; l < H; ++l) z2 = fmaf(W[oW2 + j * H + l], __shfl(h1, l, 64), z2);
+        const float h2 = z2 > 0.f ? z2 : 0.f;
+        const int k = lane & (K - 1);
+        float q = W[ob3 + k];
+#pragma unroll
+        for (int l = 0; l < H; ++l) q = fmaf(W[oW3 + k * H + l], __shfl(h2, l, 64), q);
+        const float q0 = __shfl(q, 0, 64);
+        float best = q0;
+        int ba = 0;
+#pragma unroll
+        for (int kk = 1; kk < K; ++kk) {
+            const float qk = __shfl(q, kk, 64);
+            if (qk < best) {
+                best = qk;
+                ba = kk;
+            }
+        }
+        act = (q0 - best > p.policy_margin) ? ba : 0;
+    } else if (p.policy_mode == kPolicyExplore) {
+        const uint64_t r = mix64(p.policy_seed ^ mix64(((uint64_t)(uint32_t)p.seq_base << 32) ^ (uint64_t)iter));
+        const float u = (float)(r >> 40) * (1.0f / 16777216.0f);
+        act = u < p.policy_explore ? (int)((r & 0xffffffffull) % (uint64_t)K) : 0;
+    } else if (p.policy_mode == kPolicyForced) {
+        act = p.policy_action;
+    }
+    const int rec = ld<SC>(&c->ntrace);
+    if (g.ptrace && rec < kTraceCap) {
+        float *pr = g.ptrace + (int64_t)rec * kPolRec;
+#pragma unroll
+        for (int f = 0; f < F; ++f)
+            if (lane == f) pr[f] = x[f];
+        if (lane == 0) pr[F] = (float)act;
+    }
+    if (lane == 0) c->action = act;
+    return act;
+}
+
+// ---------------------------------------------------------------------------
 // The persistent solve loop (Alg. 1 / Alg. 4 while-loop)
 // ---------------------------------------------------------------------------
 
@@ -693,6 +817,7 @@ __device__ void solve_loop(const DevGraph &g, const Team &tm, const LoopParams &
     const bool leader = tm.rank == 0 && threadIdx.x == 0;
     const bool topology = p.mode == 1;
     int64_t iter = 0;
+    const bool policy = p.policy_mode != kPolicyFixed;
     const uint64_t t0 = wall_clock64();
     for (;;) {
         // time budget: the leader raised `stop` before the last barrier, so
@@ -704,6 +829,10 @@ __device__ void solve_loop(const DevGraph &g, const Team &tm, const LoopParams &
         // --- global relabel ---
         if (leader) {
             for (int k = 0; k < 3; ++k) c->lst[k] = ListCtr{0, 0, 0, 0};
+            c->prev_pushes = c->phase_pushes;
+            c->prev_relabels = c->phase_relabels;
+            c->feat_esum = 0;
+            for (int b = 0; b < 8; ++b) c->feat_hist[b] = 0;
             c->nrelab = 0;
             c->phase_relabels = 0;
             c->phase_pushes = 0;
@@ -716,10 +845,10 @@ __device__ void solve_loop(const DevGraph &g, const Team &tm, const LoopParams &
         if (!grid_barrier(c, tm, p.barrier_ticks)) return;
         int L = 0;
         for (;;) {
-            const int cnt = ld<SC>(&c->qcount[L % 3]);
+            const int cnt = uniform(ld<SC>(&c->qcount[L % 3]));
             if (cnt == 0) break;
             if (leader) c->qcount[(L + 2) % 3] = 0;
-            bfs_level<SC>(g, tm, L, tl);
+            bfs_level<SC>(g, tm, L, policy, tl);
             if (!grid_barrier(c, tm, p.barrier_ticks)) return;
             ++L;
         }
@@ -730,8 +859,8 @@ __device__ void solve_loop(const DevGraph &g, const Team &tm, const LoopParams &
         }
         // --- termination test right after a fresh global relabel ---
         {
-            const int nl = ld<SC>(&c->lst[0].light);
-            const int nh = ld<SC>(&c->lst[0].heavy);
+            const int nl = uniform(ld<SC>(&c->lst[0].light));
+            const int nh = uniform(ld<SC>(&c->lst[0].heavy));
             if (nl + nh == 0) {
                 if (leader) c->status = kSolved;
                 break;
@@ -741,35 +870,46 @@ __device__ void solve_loop(const DevGraph &g, const Team &tm, const LoopParams &
             if (leader) c->status = kIterLimit;
             break;
         }
+        // --- limits of the coming phase (fixed rule, or the schedule's action) ---
+        int act = 0;
+        if (policy) {
+            if (tm.rank == 0 && threadIdx.x < 64) policy_decide<SC>(g, p, c, L, iter);
+            if (!grid_barrier(c, tm, p.barrier_ticks)) return;
+            act = uniform(ld<SC>(&c->action));
+        }
+        const int64_t budget = act == 0 ? p.relabel_budget : max((int64_t)64, p.relabel_budget * act_budget(act) / 4);
+        const int rpl = act == 0 ? p.rounds_per_level : max(1, p.rounds_per_level * act_rpl(act) / 2);
+        const int round_cap = p.rounds_per_level > 0 ? min(p.max_rounds, rpl * L + 16) : p.max_rounds;
+        const int stall_lim = p.stall_rounds <= 0 ? 0
+                              : act == 0      ? max(p.stall_rounds, L)
+                                              : (act_stall(act) == 0 ? 0 : max(1, max(p.stall_rounds, L) * act_stall(act) / 2));
         // --- push/relabel rounds ---
-        const int32_t rbase = p.seq_base + ld<SC>(&c->rounds);
-        const int round_cap = p.rounds_per_level > 0 ? min(p.max_rounds, p.rounds_per_level * L + 16)
-                                                     : p.max_rounds;
-        const int active0 = ld<SC>(&c->lst[0].light) + ld<SC>(&c->lst[0].heavy);
+        const int32_t rbase = p.seq_base + uniform(ld<SC>(&c->rounds));
+        const int active0 = uniform(ld<SC>(&c->lst[0].light) + ld<SC>(&c->lst[0].heavy));
         int r = 0, reason = 0;
         int64_t last_deliv = -1;
         int last_change = 0;
         for (;; ++r) {
             const int rd = r % 3, wr = (r + 1) % 3, rs = (r + 2) % 3;
-            const int nl = ld<SC>(&c->lst[rd].light);
-            const int nh = ld<SC>(&c->lst[rd].heavy);
+            const int nl = uniform(ld<SC>(&c->lst[rd].light));
+            const int nh = uniform(ld<SC>(&c->lst[rd].heavy));
             if (nl + nh == 0) break;
             if (r >= round_cap) {
                 reason = 1;
                 break;
             }
-            if (ld<SC>(&c->phase_relabels) > p.relabel_budget) {
+            if (uniform(ld<SC>(&c->phase_relabels)) > budget) {
                 reason = 2;
                 break;
             }
             // all values read here were written before the last barrier, so
             // every workgroup takes the same decision
-            const int64_t dl = ld<SC>(&c->phase_deliv);
+            const int64_t dl = uniform(ld<SC>(&c->phase_deliv));
             if (dl != last_deliv) {
                 last_deliv = dl;
                 last_change = r;
             }
-            if (p.stall_rounds > 0 && r - last_change >= max(p.stall_rounds, L)) {
+            if (stall_lim > 0 && r - last_change >= stall_lim) {
                 reason = 3;
                 break;
             }
@@ -781,7 +921,7 @@ __device__ void solve_loop(const DevGraph &g, const Team &tm, const LoopParams &
         }
         // --- RemoveInvalidEdges over the vertices that relabelled ---
         const uint64_t tr = wall_clock64();
-        const int nrel = ld<SC>(&c->nrelab);
+        const int nrel = uniform(ld<SC>(&c->nrelab));
         remove_invalid<SC>(g, tm, g.relab, nrel, p.use_gap != 0, tl);
         for (int64_t i = tm.tid(); i <= g.n; i += tm.nthreads()) g.hcount[i] = 0;
         {
@@ -795,6 +935,8 @@ __device__ void solve_loop(const DevGraph &g, const Team &tm, const LoopParams &
                 tr_rec[kTrRelabelled] = nrel;
                 tr_rec[kTrPushes] = (int32_t)min<int64_t>(ld<SC>(&c->phase_pushes), INT32_MAX);
                 tr_rec[kTrLastDeliv] = last_change;
+                if (policy && g.ptrace)
+                    g.ptrace[(int64_t)c->ntrace * kPolRec + kPolF + 1] = (float)(wall_clock64() - tb);
                 c->ntrace++;
             }
         }

@@ -12,10 +12,11 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmf.so")
 
-MF_OK, MF_EINVAL, MF_ENOMEM, MF_EDEVICE, MF_ESTATE, MF_ETIMEOUT = range(6)
+MF_OK, MF_EINVAL, MF_ENOMEM, MF_EDEVICE, MF_ESTATE, MF_ETIMEOUT, MF_EPENDING = range(7)
 MF_MODE_DATA, MF_MODE_TOPOLOGY = 0, 1
 MF_FLAG_GAP = 1
-_NAMES = {1: "MF_EINVAL", 2: "MF_ENOMEM", 3: "MF_EDEVICE", 4: "MF_ESTATE", 5: "MF_ETIMEOUT"}
+_NAMES = {1: "MF_EINVAL", 2: "MF_ENOMEM", 3: "MF_EDEVICE", 4: "MF_ESTATE", 5: "MF_ETIMEOUT",
+          6: "MF_EPENDING"}
 
 
 class MfError(RuntimeError):
@@ -64,6 +65,21 @@ class mf_batch_opts_t(C.Structure):
         return d
 
 
+class mf_server_opts_t(C.Structure):
+    _fields_ = [("device", C.c_int32), ("workers", C.c_int32), ("memory_budget", C.c_int64),
+                ("max_group_edges", C.c_int64), ("max_group_requests", C.c_int32),
+                ("reserved", C.c_int32 * 3)]
+
+
+class mf_result_t(C.Structure):
+    _fields_ = [("status", C.c_int32), ("graph", C.c_int32), ("request", C.c_int64), ("value", C.c_int64),
+                ("version", C.c_int64), ("seq", C.c_int64), ("group_size", C.c_int64),
+                ("submit_ms", C.c_double), ("start_ms", C.c_double), ("done_ms", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 # Every symbol that include/mf.h declares, with its C signature.
 _SIGS = {
     "mf_default_opts": (None, [C.POINTER(mf_opts_t)]),
@@ -105,6 +121,36 @@ _SIGS = {
     "mf_batch_min_cut": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.POINTER(C.c_int64)]),
     "mf_batch_get_stats": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(mf_stats_t)]),
     "mf_batch_set_capacities": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int64]),
+    "mf_estimate_device_bytes": (C.c_int64, [C.c_int32, C.c_int64]),
+    "mf_policy_last_error": (C.c_char_p, []),
+    "mf_policy_num_params": (C.c_int32, []),
+    "mf_policy_create": (C.c_int, [C.c_int32, C.c_uint64, C.POINTER(C.c_void_p)]),
+    "mf_policy_destroy": (None, [C.c_void_p]),
+    "mf_policy_get_params": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "mf_policy_set_params": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "mf_policy_forward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]),
+    "mf_policy_gradient": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p,
+                                     C.POINTER(C.c_float)]),
+    "mf_policy_train": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32,
+                                  C.c_float, C.POINTER(C.c_float)]),
+    "mf_set_policy": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_float, C.c_float, C.c_uint64,
+                                C.c_int32]),
+    "mf_get_policy_trace": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(C.c_int32)]),
+    "mf_server_default_opts": (None, [C.POINTER(mf_server_opts_t)]),
+    "mf_server_last_error": (C.c_char_p, []),
+    "mf_server_create": (C.c_int, [C.POINTER(mf_server_opts_t), C.POINTER(C.c_void_p)]),
+    "mf_server_destroy": (None, [C.c_void_p]),
+    "mf_server_add_graph": (C.c_int, [C.c_void_p, C.POINTER(mf_csr_t), C.c_void_p, C.c_int32, C.c_int32,
+                                      C.POINTER(mf_opts_t), C.POINTER(C.c_int32), C.POINTER(C.c_int64)]),
+    "mf_server_remove_graph": (C.c_int, [C.c_void_p, C.c_int32]),
+    "mf_server_submit": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int64,
+                                   C.POINTER(C.c_int64)]),
+    "mf_server_poll": (C.c_int, [C.c_void_p, C.c_int64, C.POINTER(mf_result_t)]),
+    "mf_server_wait": (C.c_int, [C.c_void_p, C.c_int64, C.POINTER(mf_result_t)]),
+    "mf_server_drain": (C.c_int, [C.c_void_p]),
+    "mf_server_graph_info": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+    "mf_server_memory": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                                   C.POINTER(C.c_int64)]),
 }
 
 _lib = None
@@ -337,6 +383,13 @@ class MaxFlow:
     def trace(self) -> np.ndarray:
         return mf_get_trace(self.h)
 
+    def set_policy(self, policy=None, mode=0, margin=0.0, explore=0.0, seed=0,
+                   action=0):
+        mf_set_policy(self.h, policy, mode, margin, explore, seed, action)
+
+    def policy_trace(self) -> np.ndarray:
+        return mf_get_policy_trace(self.h)
+
     def set_max_iterations(self, limit: int):
         mf_set_max_iterations(self.h, limit)
 
@@ -544,6 +597,238 @@ class Batch:
 
     def set_capacities(self, i: int, edge_ids, new_caps):
         mf_batch_set_capacities(self.b, i, edge_ids, new_caps)
+
+
+# ---------------- learned phase schedule (mf_policy_*, mf_set_policy) ----------------
+
+POLICY_FEATURES, POLICY_HIDDEN, POLICY_ACTIONS = 16, 32, 8
+MF_POLICY_FIXED, MF_POLICY_LEARNED, MF_POLICY_EXPLORE, MF_POLICY_FORCED = range(4)
+
+
+def _pcheck(rc):
+    if rc != MF_OK:
+        msg = lib().mf_policy_last_error()
+        raise MfError(rc, msg.decode() if msg else "")
+    return rc
+
+
+class Policy:
+    """The value network of the learned phase schedule (device parameters)."""
+
+    def __init__(self, seed: int = 0, device: int = 0):
+        out = C.c_void_p()
+        _pcheck(lib().mf_policy_create(int(device), int(seed) & (2**64 - 1), C.byref(out)))
+        self.p = out
+        self.n_params = int(lib().mf_policy_num_params())
+
+    def close(self):
+        if self.p:
+            lib().mf_policy_destroy(self.p)
+            self.p = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def params(self) -> np.ndarray:
+        out = np.zeros(self.n_params, dtype=np.float32)
+        _pcheck(lib().mf_policy_get_params(self.p, _ptr(out)))
+        return out
+
+    def set_params(self, theta):
+        theta = np.ascontiguousarray(theta, dtype=np.float32)
+        if theta.shape != (self.n_params,):
+            raise ValueError("wrong parameter count")
+        _pcheck(lib().mf_policy_set_params(self.p, _ptr(theta)))
+
+    def forward(self, X) -> np.ndarray:
+        X = np.ascontiguousarray(X, dtype=np.float32).reshape(-1, POLICY_FEATURES)
+        Q = np.zeros((X.shape[0], POLICY_ACTIONS), dtype=np.float32)
+        _pcheck(lib().mf_policy_forward(self.p, _ptr(X), X.shape[0], _ptr(Q)))
+        return Q
+
+    def gradient(self, X, actions, targets):
+        X = np.ascontiguousarray(X, dtype=np.float32).reshape(-1, POLICY_FEATURES)
+        a = np.ascontiguousarray(actions, dtype=np.int32)
+        y = np.ascontiguousarray(targets, dtype=np.float32)
+        g = np.zeros(self.n_params, dtype=np.float32)
+        loss = C.c_float()
+        _pcheck(lib().mf_policy_gradient(self.p, _ptr(X), _ptr(a), _ptr(y), X.shape[0], _ptr(g), C.byref(loss)))
+        return float(loss.value), g
+
+    def train(self, X, actions, targets, steps: int = 500, lr: float = 3e-3) -> float:
+        X = np.ascontiguousarray(X, dtype=np.float32).reshape(-1, POLICY_FEATURES)
+        a = np.ascontiguousarray(actions, dtype=np.int32)
+        y = np.ascontiguousarray(targets, dtype=np.float32)
+        loss = C.c_float()
+        _pcheck(lib().mf_policy_train(self.p, _ptr(X), _ptr(a), _ptr(y), X.shape[0], int(steps), float(lr),
+                                      C.byref(loss)))
+        return float(loss.value)
+
+
+def mf_set_policy(h, policy: "Policy | None", mode: int, margin: float = 0.0, explore: float = 0.0,
+                  seed: int = 0, action: int = 0):
+    return _check(lib().mf_set_policy(h, policy.p if policy is not None else None, int(mode), float(margin),
+                                      float(explore), int(seed) & (2**64 - 1), int(action)), h)
+
+
+def mf_get_policy_trace(h, max_phases: int = 256) -> np.ndarray:
+    """float32[phases, 18]: features, action taken, phase duration (ms)."""
+    out = np.zeros((max_phases, POLICY_FEATURES + 2), dtype=np.float32)
+    n = C.c_int32()
+    _check(lib().mf_get_policy_trace(h, _ptr(out), max_phases, C.byref(n)), h)
+    return out[: min(n.value, max_phases)]
+
+
+# ---------------- serving runtime (mf_server_*) ----------------
+
+def _scheck(rc):
+    if rc not in (MF_OK, MF_EPENDING):
+        msg = lib().mf_server_last_error()
+        raise MfError(rc, msg.decode() if msg else "")
+    return rc
+
+
+def mf_estimate_device_bytes(n: int, m: int) -> int:
+    return int(lib().mf_estimate_device_bytes(int(n), int(m)))
+
+
+def mf_server_default_opts() -> mf_server_opts_t:
+    o = mf_server_opts_t()
+    lib().mf_server_default_opts(C.byref(o))
+    return o
+
+
+def mf_server_create(opts: mf_server_opts_t | None = None):
+    out = C.c_void_p()
+    _scheck(lib().mf_server_create(C.byref(opts) if opts is not None else None, C.byref(out)))
+    return out
+
+
+def mf_server_destroy(s):
+    lib().mf_server_destroy(s)
+
+
+def mf_server_add_graph(s, g, cap=None, opts: mf_opts_t | None = None):
+    row_ptr = np.ascontiguousarray(g.row_ptr, dtype=np.int64)
+    col = np.ascontiguousarray(g.col, dtype=np.int32)
+    cp = np.ascontiguousarray(g.cap if cap is None else cap, dtype=np.int32)
+    csr = mf_csr_t(int(g.n), int(col.shape[0]), row_ptr.ctypes.data, col.ctypes.data)
+    gid = C.c_int32()
+    val = C.c_int64()
+    _scheck(lib().mf_server_add_graph(s, C.byref(csr), _ptr(cp), int(g.s), int(g.t),
+                                      C.byref(opts) if opts is not None else None, C.byref(gid), C.byref(val)))
+    return int(gid.value), int(val.value)
+
+
+def mf_server_remove_graph(s, graph_id: int):
+    return _scheck(lib().mf_server_remove_graph(s, int(graph_id)))
+
+
+def mf_server_submit(s, graph_id: int, edge_ids, new_caps) -> int:
+    ids = np.ascontiguousarray(edge_ids, dtype=np.int64)
+    caps = np.ascontiguousarray(new_caps, dtype=np.int32)
+    if ids.shape != caps.shape:
+        raise ValueError("edge_ids and new_caps differ in length")
+    rid = C.c_int64()
+    _scheck(lib().mf_server_submit(s, int(graph_id), _ptr(ids), _ptr(caps), ids.shape[0], C.byref(rid)))
+    return int(rid.value)
+
+
+def mf_server_poll(s, request_id: int):
+    r = mf_result_t()
+    rc = _scheck(lib().mf_server_poll(s, int(request_id), C.byref(r)))
+    return None if rc == MF_EPENDING else r.as_dict()
+
+
+def mf_server_wait(s, request_id: int) -> dict:
+    r = mf_result_t()
+    _scheck(lib().mf_server_wait(s, int(request_id), C.byref(r)))
+    return r.as_dict()
+
+
+def mf_server_drain(s):
+    return _scheck(lib().mf_server_drain(s))
+
+
+def mf_server_graph_info(s, graph_id: int):
+    v = C.c_int64()
+    val = C.c_int64()
+    _scheck(lib().mf_server_graph_info(s, int(graph_id), C.byref(v), C.byref(val)))
+    return int(v.value), int(val.value)
+
+
+def mf_server_memory(s):
+    r, b, c = C.c_int64(), C.c_int64(), C.c_int64()
+    _scheck(lib().mf_server_memory(s, C.byref(r), C.byref(b), C.byref(c)))
+    return {"reserved": int(r.value), "budget": int(b.value), "commits": int(c.value)}
+
+
+class Server:
+    """Owns one serving runtime."""
+
+    def __init__(self, workers=4, memory_budget=0, max_group_edges=1 << 20, max_group_requests=64, device=0):
+        o = mf_server_default_opts()
+        o.device = device
+        o.workers = workers
+        o.memory_budget = memory_budget
+        o.max_group_edges = max_group_edges
+        o.max_group_requests = max_group_requests
+        self.s = mf_server_create(o)
+
+    def close(self):
+        if self.s:
+            mf_server_destroy(self.s)
+            self.s = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def add_graph(self, g, cap=None, **opts):
+        o = None
+        if opts:
+            o = mf_default_opts()
+            for k, v in opts.items():
+                setattr(o, k, v)
+        return mf_server_add_graph(self.s, g, cap, o)
+
+    def remove_graph(self, graph_id: int):
+        mf_server_remove_graph(self.s, graph_id)
+
+    def submit(self, graph_id: int, edge_ids, new_caps) -> int:
+        return mf_server_submit(self.s, graph_id, edge_ids, new_caps)
+
+    def poll(self, request_id: int):
+        return mf_server_poll(self.s, request_id)
+
+    def wait(self, request_id: int) -> dict:
+        return mf_server_wait(self.s, request_id)
+
+    def drain(self):
+        mf_server_drain(self.s)
+
+    def graph_info(self, graph_id: int):
+        return mf_server_graph_info(self.s, graph_id)
+
+    def memory(self) -> dict:
+        return mf_server_memory(self.s)
 
 
 # Load at import: a missing or broken library is an ImportError, never a fallback.

@@ -265,3 +265,24 @@ def c4_instances(count: int = 256, seed=SEED_BASE + 3):
             n = int(round(1000 * 50 ** u))
             out.append(random_graph(n, 8 * n, 1, 1000, int(seed) * 1000 + i, s=0, t=n - 1))
     return out
+
+
+def c5_rmat22(seed=SEED_BASE + 4) -> Graph:
+    """R-MAT scale 22 (4,194,304 vertices, 67,108,864 edges), generator as C3."""
+    return rmat(22, 16, seed)
+
+
+def request_stream(g: Graph, count: int, seed, k_lo: int = 10, k_hi: int = 100_000, inc_hi: int = 1000):
+    """Yield `count` update requests (ids, new_caps) for a served graph: request
+    j has k = round(k_lo * (k_hi/k_lo)^u) distinct edges, u ~ U[0,1] (log-uniform),
+    half raised by U[1, inc_hi] and half lowered to U[0, c]; capacities evolve
+    as the requests are applied in order."""
+    cur = g.cap.copy()
+    for j in range(count):
+        rng = rng_for(seed, 2, j)
+        u = float(rng.random())
+        k = min(g.m, max(1, int(round(k_lo * (k_hi / k_lo) ** u))))
+        ids, new = mixed_batch(cur, k, inc_hi, rng)
+        cur[ids] = new
+        yield ids, new
+
