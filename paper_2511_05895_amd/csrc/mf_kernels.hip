@@ -293,10 +293,14 @@ __device__ void bfs_level(const DevGraph &g, const Team &tm, int L, bool feats, 
     const int64_t gwave = tm.wave();
     const int64_t nwaves = tm.nwaves();
     const int n = g.n;
-    for (int64_t base = gwave * 64; base < cnt; base += nwaves * 64) {
+    // items per wavefront: up to 64, fewer when the frontier is small, so
+    // that every wavefront of the team takes part and each one expands as
+    // few 64-arc steps one after another as possible
+    const int64_t ipw = min((int64_t)64, max((int64_t)1, ((int64_t)cnt + nwaves - 1) / nwaves));
+    for (int64_t base = gwave * ipw; base < cnt; base += nwaves * ipw) {
         const int64_t idx = base + lane;
         int beg = 0, len = 0;
-        if (idx < cnt) {
+        if (lane < ipw && idx < cnt) {
             const int2 it = qin[idx];  // arc range {first, end} of one item
             beg = it.x;
             len = it.y - it.x;
@@ -448,67 +452,24 @@ __device__ __forceinline__ void push_arc(const DevGraph &g, const RoundCtx &rc, 
     }
 }
 
-// One lane visits vertex u.  Returns the number of relabels.
-template <int SC>
-__device__ int discharge_lane(const DevGraph &g, int u, int kc, const RoundCtx &rc, Tally &tl,
-                              int64_t &to_t) {
+// A group of G lanes (G = 64: a wavefront) visits vertex u: the lanes scan
+// its arcs G at a time for the lowest residual neighbour height, and the push
+// pass hands the excess to the lowest arcs in arc order with a prefix sum of
+// their residual capacities over the group.  u < 0: the group idles.  Every
+// loop bound is uniform inside the group, so its lanes stay converged and the
+// shuffles of width G stay inside it.  Returns relabels (on the group's lane
+// 0).
+template <int SC, int G>
+__device__ int discharge_group(const DevGraph &g, int u, int kc, const RoundCtx &rc, Tally &tl,
+                               int64_t &to_t) {
+    const int gl = lane_id() & (G - 1);
+    if (u < 0) return 0;
     const int n = g.n;
     const int beg = g.row_ptr[u], end = g.row_ptr[u + 1];
     int hu = g.h[u];
     int relabels = 0;
     if (rc.use_gap && hu < n && hu > ld<SC>(&g.ctrl->gap)) {  // above a gap: cut off
-        add<SC>(&g.hcount[hu], -1);
-        hu = n;
-        g.h[u] = n;
-    }
-    for (int cyc = 0; cyc < kc && hu < n; ++cyc) {
-        int64_t eu = ld<SC>(&g.e[u]);
-        if (eu <= 0) break;
-        tl.pr_cyc++;
-        int hmin = INT32_MAX;
-        for (int a = beg; a < end; ++a) {
-            const int2 r = g.arc[a];
-            if (r.y > 0) hmin = min(hmin, g.h[r.x]);
-        }
-        tl.pr_a += end - beg;
-        if (hmin == INT32_MAX) break;
-        if (hu > hmin) {
-            int64_t sent = 0;
-            for (int a = beg; a < end && sent < eu; ++a) {
-                const int2 r = g.arc[a];
-                if (r.y <= 0 || g.h[r.x] != hmin) continue;
-                const int32_t cfl = ld<SC>(cf_ptr(g.arc, a));
-                const int64_t d = min(eu - sent, (int64_t)cfl);
-                if (d <= 0) continue;
-                push_arc<SC>(g, rc, a, r.x, (int32_t)d, to_t, tl);
-                sent += d;
-                tl.push++;
-            }
-            if (sent) add<SC>(&g.e[u], -sent);
-        } else {
-            hu = relabel_to<SC>(g, u, hu, hmin, rc.use_gap);
-            tl.relabel++;
-            relabels++;
-            note_relabel<SC>(g, u, rc.phase_id);
-        }
-    }
-    if (hu < n && ld<SC>(&g.e[u]) > 0) list_add<SC>(g, rc, u);
-    return relabels;
-}
-
-// One wavefront visits vertex u (long arc list).  Lanes scan the arcs; the
-// push pass hands the excess to the lowest arcs in arc order with a wavefront
-// prefix sum of their residual capacities.  Returns relabels (on lane 0).
-template <int SC>
-__device__ int discharge_wave(const DevGraph &g, int u, int kc, const RoundCtx &rc, Tally &tl,
-                              int64_t &to_t) {
-    const int lane = lane_id();
-    const int n = g.n;
-    const int beg = g.row_ptr[u], end = g.row_ptr[u + 1];
-    int hu = g.h[u];
-    int relabels = 0;
-    if (rc.use_gap && hu < n && hu > ld<SC>(&g.ctrl->gap)) {  // above a gap: cut off
-        if (lane == 0) {
+        if (gl == 0) {
             add<SC>(&g.hcount[hu], -1);
             g.h[u] = n;
         }
@@ -516,23 +477,23 @@ __device__ int discharge_wave(const DevGraph &g, int u, int kc, const RoundCtx &
     }
     for (int cyc = 0; cyc < kc && hu < n; ++cyc) {
         int64_t eu = 0;
-        if (lane == 0) eu = ld<SC>(&g.e[u]);
-        eu = __shfl(eu, 0, 64);
+        if (gl == 0) eu = ld<SC>(&g.e[u]);
+        eu = __shfl(eu, 0, G);
         if (eu <= 0) break;
-        if (lane == 0) tl.pr_cyc++;
+        if (gl == 0) tl.pr_cyc++;
         int hmin = INT32_MAX;
-        for (int a = beg + lane; a < end; a += 64) {
+        for (int a = beg + gl; a < end; a += G) {
             const int2 r = g.arc[a];
             if (r.y > 0) hmin = min(hmin, g.h[r.x]);
         }
-        if (lane == 0) tl.pr_a += end - beg;
+        if (gl == 0) tl.pr_a += end - beg;
 #pragma unroll
-        for (int d = 32; d >= 1; d >>= 1) hmin = min(hmin, __shfl_xor(hmin, d, 64));
+        for (int d = G / 2; d >= 1; d >>= 1) hmin = min(hmin, __shfl_xor(hmin, d, G));
         if (hmin == INT32_MAX) break;
         if (hu > hmin) {
             int64_t sent = 0;
-            for (int base = beg; base < end && sent < eu; base += 64) {
-                const int a = base + lane;
+            for (int base = beg; base < end && sent < eu; base += G) {
+                const int a = base + gl;
                 int64_t c = 0;
                 int v = -1;
                 if (a < end) {
@@ -542,12 +503,12 @@ __device__ int discharge_wave(const DevGraph &g, int u, int kc, const RoundCtx &
                         v = r.x;
                     }
                 }
-                // inclusive prefix sum of c over the wavefront, in arc order
+                // inclusive prefix sum of c over the group, in arc order
                 int64_t incl = c;
 #pragma unroll
-                for (int d = 1; d < 64; d <<= 1) {
-                    const int64_t y = __shfl_up(incl, d, 64);
-                    if (lane >= d) incl += y;
+                for (int d = 1; d < G; d <<= 1) {
+                    const int64_t y = __shfl_up(incl, d, G);
+                    if (gl >= d) incl += y;
                 }
                 const int64_t room = eu - sent;
                 const int64_t excl = incl - c;
@@ -556,24 +517,28 @@ __device__ int discharge_wave(const DevGraph &g, int u, int kc, const RoundCtx &
                     push_arc<SC>(g, rc, a, v, (int32_t)d, to_t, tl);
                     tl.push++;
                 }
-                const int64_t tot = min(__shfl(incl, 63, 64), room);
+                const int64_t tot = min(__shfl(incl, G - 1, G), room);
                 sent += tot;
             }
-            if (lane == 0 && sent) add<SC>(&g.e[u], -sent);
+            if (gl == 0 && sent) add<SC>(&g.e[u], -sent);
         } else {
             int hn = 0;
-            if (lane == 0) {
+            if (gl == 0) {
                 hn = relabel_to<SC>(g, u, hu, hmin, rc.use_gap);
                 tl.relabel++;
                 note_relabel<SC>(g, u, rc.phase_id);
             }
-            hu = __shfl(hn, 0, 64);
+            hu = __shfl(hn, 0, G);
             relabels++;
         }
     }
-    if (lane == 0 && hu < n && ld<SC>(&g.e[u]) > 0) list_add<SC>(g, rc, u);
-    return lane == 0 ? relabels : 0;
+    if (gl == 0 && hu < n && ld<SC>(&g.e[u]) > 0) list_add<SC>(g, rc, u);
+    return gl == 0 ? relabels : 0;
 }
+
+// Lanes per vertex with a short arc list (at most kLightMaxDeg arcs): the
+// arcs of a typical vertex load in one step instead of one after another.
+constexpr int kLightGroup = 8;
 
 // Excess pushed into t by the lanes of a wavefront, added with one atomic.
 template <int SC>
@@ -607,7 +572,12 @@ __device__ void pr_round(const DevGraph &g, const Team &tm, int rd, int nl, int 
     const int32_t *lst = g.list[rd];
     int64_t to_t = 0, rl = 0;
     const uint32_t push0 = tl.push;
-    for (int64_t i = gtid; i < nl; i += stride) rl += discharge_lane<SC>(g, lst[i], kc, rc, tl, to_t);
+    {
+        const int64_t grp = gtid / kLightGroup, ngrp = stride / kLightGroup;
+        const int64_t trips = (nl + ngrp - 1) / ngrp;  // the same for every group
+        for (int64_t k = 0, i = grp; k < trips; ++k, i += ngrp)
+            rl += discharge_group<SC, kLightGroup>(g, i < nl ? lst[i] : -1, kc, rc, tl, to_t);
+    }
     flush_to_t<SC>(g, to_t);
     int32_t *grab = &g.ctrl->lst[rd].grab;
     for (; nh > 0;) {
@@ -615,7 +585,7 @@ __device__ void pr_round(const DevGraph &g, const Team &tm, int rd, int nl, int 
         if (lane_id() == 0) idx = fetch_add<SC>(grab, 1);
         idx = __shfl(idx, 0, 64);
         if (idx >= nh) break;
-        rl += discharge_wave<SC>(g, lst[g.n - 1 - idx], kc, rc, tl, to_t);
+        rl += discharge_group<SC, 64>(g, lst[g.n - 1 - idx], kc, rc, tl, to_t);
     }
     flush_to_t<SC>(g, to_t);
     flush_relabels<SC>(g.ctrl, rl, (int64_t)(tl.push - push0), tl.deliv);
@@ -630,15 +600,18 @@ __device__ void pr_round_topology(const DevGraph &g, const Team &tm, int kc, con
     const int64_t stride = tm.nthreads();
     int64_t to_t = 0, rl = 0;
     const uint32_t push0 = tl.push;
-    for (int64_t i = gtid; i < g.n; i += stride) {
-        const int u = (int)i;
-        if (u == g.s || u == g.t) continue;
-        if (g.row_ptr[u + 1] - g.row_ptr[u] > kLightMaxDeg) continue;
-        rl += discharge_lane<SC>(g, u, kc, rc, tl, to_t);
+    {
+        const int64_t grp = gtid / kLightGroup, ngrp = stride / kLightGroup;
+        const int64_t trips = ((int64_t)g.n + ngrp - 1) / ngrp;
+        for (int64_t k = 0, i = grp; k < trips; ++k, i += ngrp) {
+            int u = (int)i;
+            if (i >= g.n || u == g.s || u == g.t || g.row_ptr[u + 1] - g.row_ptr[u] > kLightMaxDeg) u = -1;
+            rl += discharge_group<SC, kLightGroup>(g, u, kc, rc, tl, to_t);
+        }
     }
     flush_to_t<SC>(g, to_t);
     for (int64_t i = tm.wave(); i < g.n_heavy_all; i += tm.nwaves())
-        rl += discharge_wave<SC>(g, g.heavy_all[i], kc, rc, tl, to_t);
+        rl += discharge_group<SC, 64>(g, g.heavy_all[i], kc, rc, tl, to_t);
     flush_to_t<SC>(g, to_t);
     flush_relabels<SC>(g.ctrl, rl, (int64_t)(tl.push - push0), tl.deliv);
     tl.deliv = 0;
