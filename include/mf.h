@@ -77,7 +77,7 @@ typedef struct {
     int32_t relabel_budget; /* relabels allowed between two global relabels
                                before the next one is forced; 0 = max(1024, n/2) */
     int32_t rounds_per_level; /* a phase also ends after this many rounds per
-                               level of the BFS that began it (+16); 0 = 2,
+                               level of the BFS that began it (+16); 0 = 1,
                                < 0 = no such cap                             */
     int32_t flags;          /* MF_FLAG_* bits                                 */
     int32_t stall_rounds;   /* a phase also ends once no excess has reached t

@@ -44,7 +44,7 @@ struct mf_handle {
     int64_t barrier_ticks = 0;
     int64_t relabel_budget = 0;
     int32_t max_rounds = 0;
-    int32_t rounds_per_level = 2;
+    int32_t rounds_per_level = 1;
     int32_t use_gap = 0;
     int32_t stall_rounds = 3;
     double tick_ms = 1e-5;  // one wall-clock tick in ms
@@ -311,7 +311,7 @@ MF_API int mf_create(const mf_csr_t *g, const int32_t *cap, int32_t s, int32_t t
     const int64_t budget_ms = o.time_budget_ms > 0 ? o.time_budget_ms : 60000;
     h->max_rounds = o.max_rounds > 0 ? o.max_rounds : 65536;
     h->relabel_budget = o.relabel_budget > 0 ? o.relabel_budget : std::max<int64_t>(1024, n / 2);
-    h->rounds_per_level = o.rounds_per_level == 0 ? 2 : (o.rounds_per_level < 0 ? 0 : o.rounds_per_level);
+    h->rounds_per_level = o.rounds_per_level == 0 ? 1 : (o.rounds_per_level < 0 ? 0 : o.rounds_per_level);
     h->use_gap = (o.flags & MF_FLAG_GAP) ? 1 : 0;
     h->stall_rounds = o.stall_rounds == 0 ? 3 : (o.stall_rounds < 0 ? 0 : o.stall_rounds);
     h->kc = o.kernel_cycles > 0 ? o.kernel_cycles

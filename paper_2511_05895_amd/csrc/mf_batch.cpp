@@ -473,7 +473,7 @@ MF_API int mf_batch_create(int32_t count, const int32_t *n, const int64_t *m, co
     pr.relabel_budget = 0;  // per instance: max(1024, n/2)
     pr.max_rounds = 65536;
     pr.seq_base = 1;
-    pr.rounds_per_level = 2;
+    pr.rounds_per_level = 1;
     int rc = apply_config(b);
     if (rc) {
         std::string msg = b->err;

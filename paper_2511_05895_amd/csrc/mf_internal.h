@@ -75,8 +75,10 @@ struct alignas(128) PaddedU32 {
 
 // One active-vertex list of the push/relabel rounds: vertices with short arc
 // lists fill items[0, light) from the front, the others items[n-heavy, n) from
-// the back; `grab` hands out the long-list vertices to wavefronts.
-struct ListCtr {
+// the back; `grab` hands out the long-list vertices to wavefronts.  The BFS
+// reserves {light, heavy} together as one 64-bit counter (light in the low
+// half).
+struct alignas(16) ListCtr {
     int32_t light;
     int32_t heavy;
     int32_t grab;
@@ -86,8 +88,7 @@ struct ListCtr {
 // Device control block: barrier words on their own cache lines, then loop
 // counters.  Reset by k_reset_ctrl before every solving call.
 struct Ctrl {
-    PaddedU32 bar_count;
-    PaddedU32 bar_gen;
+    PaddedU32 bar_count;  // monotonic barrier arrivals of the launch
     PaddedU32 abort;
     int32_t qcount[4];  // frontier items per BFS level, triple-buffered
     ListCtr lst[3];     // active lists of the rounds, triple-buffered

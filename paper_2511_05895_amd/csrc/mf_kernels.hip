@@ -160,29 +160,35 @@ struct Team {
     __device__ int64_t nwaves() const { return (int64_t)size * (blockDim.x >> 6); }
 };
 
-// Barrier of a team with a bounded wait.  Returns false when the wait ran out
-// (wall clock, `limit` ticks) or another workgroup aborted; the caller must then
-// leave the kernel, so every workgroup ends even if co-residency ever failed.
-__device__ bool grid_barrier(Ctrl *c, const Team &tm, int64_t limit) {
+// Barrier of a team with a bounded wait.  Arrivals count up one monotonic
+// counter (cleared before every launch): barrier number `epoch` (0, 1, ...)
+// is complete once it reaches (epoch + 1) * size.  One release fence before
+// the arrival and one acquire fence after the wait; the polls themselves are
+// relaxed loads, so waiting does not keep invalidating the caches that the
+// team's other workgroups are still working from.  Returns false when the
+// wait ran out (wall clock, `limit` ticks) or another workgroup aborted; the
+// caller must then leave the kernel, so every workgroup ends even if
+// co-residency ever failed.  Every thread of every workgroup of the team calls
+// it with the same epoch, which it advances.
+__device__ bool grid_barrier(Ctrl *c, const Team &tm, uint32_t &epoch, int64_t limit) {
     if (tm.size == 1) {
         __syncthreads();
         return true;
     }
     __shared__ int s_ok;
     __syncthreads();
+    const uint32_t target = (epoch + 1u) * (uint32_t)tm.size;
+    ++epoch;
     if (threadIdx.x == 0) {
         int ok = 1;
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        uint32_t gen = __hip_atomic_load(&c->bar_gen.v, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-        uint32_t arrived =
-            __hip_atomic_fetch_add(&c->bar_count.v, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        if (arrived == (uint32_t)tm.size - 1) {
-            __hip_atomic_store(&c->bar_count.v, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&c->bar_gen.v, gen + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
+        const uint32_t before =
+            __hip_atomic_fetch_add(&c->bar_count.v, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if ((int32_t)(before + 1u - target) < 0) {
             const uint64_t tw = wall_clock64();
             uint32_t spins = 0;
-            while (__hip_atomic_load(&c->bar_gen.v, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+            while ((int32_t)(__hip_atomic_load(&c->bar_count.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) -
+                             target) < 0) {
                 __builtin_amdgcn_s_sleep(1);
                 if ((++spins & 255u) == 0) {
                     if (__hip_atomic_load(&c->abort.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
@@ -284,10 +290,9 @@ __device__ __forceinline__ void feature_tally(Ctrl *c, bool active, int64_t ev) 
 // frontier items of the next level; those with positive excess go to the
 // active worklist (A of Alg. 1: e > 0 and h < |V|, s and t excluded).
 template <int SC>
-__device__ void bfs_level(const DevGraph &g, const Team &tm, int L, bool feats, Tally &tl) {
+__device__ void bfs_level(const DevGraph &g, const Team &tm, int L, int cnt, bool feats, Tally &tl) {
     const int2 *__restrict__ qin = g.q[L & 1];
     int2 *qout = g.q[(L + 1) & 1];
-    const int cnt = ld<SC>(&g.ctrl->qcount[L % 3]);
     int32_t *qout_count = &g.ctrl->qcount[(L + 1) % 3];
     const int lane = lane_id();
     const int64_t gwave = tm.wave();
@@ -347,17 +352,31 @@ __device__ void bfs_level(const DevGraph &g, const Team &tm, int L, bool feats, 
             if (feats) feature_tally<SC>(g.ctrl, active, ev);
             const int vdeg = vend - vbeg;
             const int ndisc = __popcll(__ballot(disc));
-            if (lane_id() == 0 && ndisc) add<SC>(&g.hcount[L + 1], ndisc);
+            if (lane == 0 && ndisc) add<SC>(&g.hcount[L + 1], ndisc);
+            // reservations of this step: frontier items, and both halves of
+            // the active list through one packed 64-bit counter {light, heavy};
+            // one lane issues them back to back so their round trips overlap
             const int c = disc ? n_items(vdeg) : 0;
-            const int qb = wave_appendn<SC>(qout_count, c);
-            for (int k = 0; k < c; ++k)
-                qout[qb + k] = make_int2(vbeg + k * kChunk, min(vbeg + (k + 1) * kChunk, vend));
+            const int cincl = wave_incl_scan(c);
+            const int ctotal = __shfl(cincl, 63, 64);
             const bool light = active && vdeg <= kLightMaxDeg;
             const bool heavy = active && vdeg > kLightMaxDeg;
-            const int sl = wave_append1<SC>(&g.ctrl->lst[0].light, light);
-            if (light) g.list[0][sl] = v;
-            const int sh = wave_append1<SC>(&g.ctrl->lst[0].heavy, heavy);
-            if (heavy) g.list[0][n - 1 - sh] = v;
+            const uint64_t lm = __ballot(light), hm = __ballot(heavy);
+            int qbase = 0;
+            int64_t lbase = 0;
+            if (lane == 63) {
+                if (ctotal) qbase = fetch_add<SC>(qout_count, ctotal);
+                if (lm | hm)
+                    lbase = fetch_add<SC>(reinterpret_cast<int64_t *>(&g.ctrl->lst[0]),
+                                          ((int64_t)__popcll(hm) << 32) | (int64_t)__popcll(lm));
+            }
+            qbase = __shfl(qbase, 63, 64);
+            lbase = __shfl(lbase, 63, 64);
+            const int qb = qbase + cincl - c;
+            for (int k = 0; k < c; ++k)
+                qout[qb + k] = make_int2(vbeg + k * kChunk, min(vbeg + (k + 1) * kChunk, vend));
+            if (light) g.list[0][(int)(uint32_t)lbase + mask_rank(lm)] = v;
+            if (heavy) g.list[0][n - 1 - ((int)(lbase >> 32) + mask_rank(hm))] = v;
         }
     }
 }
@@ -790,6 +809,7 @@ __device__ void solve_loop(const DevGraph &g, const Team &tm, const LoopParams &
     const bool leader = tm.rank == 0 && threadIdx.x == 0;
     const bool topology = p.mode == 1;
     int64_t iter = 0;
+    uint32_t bar_epoch = 0;  // barriers this launch has passed
     const bool policy = p.policy_mode != kPolicyFixed;
     const uint64_t t0 = wall_clock64();
     for (;;) {
@@ -815,14 +835,14 @@ __device__ void solve_loop(const DevGraph &g, const Team &tm, const LoopParams &
         }
         const uint64_t tb = wall_clock64();
         bfs_roots<SC>(g, tm, tl);
-        if (!grid_barrier(c, tm, p.barrier_ticks)) return;
+        if (!grid_barrier(c, tm, bar_epoch, p.barrier_ticks)) return;
         int L = 0;
         for (;;) {
             const int cnt = uniform(ld<SC>(&c->qcount[L % 3]));
             if (cnt == 0) break;
             if (leader) c->qcount[(L + 2) % 3] = 0;
-            bfs_level<SC>(g, tm, L, policy, tl);
-            if (!grid_barrier(c, tm, p.barrier_ticks)) return;
+            bfs_level<SC>(g, tm, L, cnt, policy, tl);
+            if (!grid_barrier(c, tm, bar_epoch, p.barrier_ticks)) return;
             ++L;
         }
         const uint64_t tp = wall_clock64();
@@ -847,7 +867,7 @@ __device__ void solve_loop(const DevGraph &g, const Team &tm, const LoopParams &
         int act = 0;
         if (policy) {
             if (tm.rank == 0 && threadIdx.x < 64) policy_decide<SC>(g, p, c, L, iter);
-            if (!grid_barrier(c, tm, p.barrier_ticks)) return;
+            if (!grid_barrier(c, tm, bar_epoch, p.barrier_ticks)) return;
             act = uniform(ld<SC>(&c->action));
         }
         const int64_t budget = act == 0 ? p.relabel_budget : max((int64_t)64, p.relabel_budget * act_budget(act) / 4);
@@ -890,7 +910,7 @@ __device__ void solve_loop(const DevGraph &g, const Team &tm, const LoopParams &
             const RoundCtx rc{g.list[wr], &c->lst[wr], rbase + r + 1, rbase, p.use_gap != 0};
             if (topology) pr_round_topology<SC>(g, tm, p.kc, rc, tl);
             else pr_round<SC>(g, tm, rd, nl, nh, p.kc, rc, tl);
-            if (!grid_barrier(c, tm, p.barrier_ticks)) return;
+            if (!grid_barrier(c, tm, bar_epoch, p.barrier_ticks)) return;
         }
         // --- RemoveInvalidEdges over the vertices that relabelled ---
         const uint64_t tr = wall_clock64();
@@ -925,7 +945,7 @@ __device__ void solve_loop(const DevGraph &g, const Team &tm, const LoopParams &
             if ((int64_t)(wall_clock64() - t0) > p.deadline_ticks) c->stop = 1;
         }
         flush_tally<SC>(c, tl);
-        if (!grid_barrier(c, tm, p.barrier_ticks)) return;
+        if (!grid_barrier(c, tm, bar_epoch, p.barrier_ticks)) return;
         ++iter;
     }
     // --- value: e(t) plus the deficits of vertices other than s and t ---
