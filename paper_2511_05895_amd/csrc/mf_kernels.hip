@@ -326,7 +326,8 @@ __device__ void bfs_level(const DevGraph &g, const Team &tm, int L, int cnt, boo
             const int obeg = __shfl(beg, o, 64);
             const int oexcl = __shfl(excl, o, 64);
             bool disc = false;
-            int v = -1;
+            int v = -1, vbeg = 0, vend = 0;
+            int64_t ev = 0;
             if (j < total) {
                 const int a = obeg + (j - oexcl);
                 // the head and the twin index come in one step, the head's height
@@ -337,17 +338,21 @@ __device__ void bfs_level(const DevGraph &g, const Team &tm, int L, int cnt, boo
                 const int hv = g.h[v];
                 const int cft = g.arc[tw].y;
                 tl.bfs_a++;
-                if (v != g.s && hv == n && cft > 0) disc = cas<SC>(&g.h[v], n, L + 1);
+                if (v != g.s && hv == n && cft > 0) {
+                    // the candidate's row bounds and excess load alongside the
+                    // compare-and-swap that decides the discovery
+                    vbeg = g.row_ptr[v];
+                    vend = g.row_ptr[v + 1];
+                    ev = g.e[v];
+                    disc = cas<SC>(&g.h[v], n, L + 1);
+                }
             }
-            int vbeg = 0, vend = 0;
             bool active = false;
-            int64_t ev = 0;
             if (disc) {
-                vbeg = g.row_ptr[v];
-                vend = g.row_ptr[v + 1];
-                ev = g.e[v];
                 active = (v != g.t) && ev > 0;
                 tl.bfs_v++;
+            } else {
+                vbeg = vend = 0;
             }
             if (feats) feature_tally<SC>(g.ctrl, active, ev);
             const int vdeg = vend - vbeg;
@@ -410,8 +415,8 @@ struct RoundCtx {
 // Add v to the next round's list unless it is already there.
 template <int SC>
 __device__ __forceinline__ void list_add(const DevGraph &g, const RoundCtx &rc, int v) {
+    const int deg = g.row_ptr[v + 1] - g.row_ptr[v];  // read alongside the exchange
     if (xchg<SC>(&g.mark[v], rc.next_id) == rc.next_id) return;
-    const int deg = g.row_ptr[v + 1] - g.row_ptr[v];
     if (deg <= kLightMaxDeg) {
         const int slot = fetch_add<SC>(&rc.next_ctr->light, 1);
         rc.next[slot] = v;
@@ -458,10 +463,10 @@ __device__ __forceinline__ int relabel_to(const DevGraph &g, int u, int ho, int 
 // twin; excess moves from u to v except that the excess taken from u is
 // subtracted by the caller (one atomic per visit chunk).
 template <int SC>
-__device__ __forceinline__ void push_arc(const DevGraph &g, const RoundCtx &rc, int a, int v,
+__device__ __forceinline__ void push_arc(const DevGraph &g, const RoundCtx &rc, int a, int tw, int v,
                                          int32_t d, int64_t &to_t, Tally &tl) {
     add<SC>(cf_ptr(g.arc, a), -d);
-    add<SC>(cf_ptr(g.arc, g.twin[a]), d);
+    add<SC>(cf_ptr(g.arc, tw), d);
     if (v == g.t) {
         to_t += d;
     } else {
@@ -494,10 +499,12 @@ __device__ int discharge_group(const DevGraph &g, int u, int kc, const RoundCtx 
         }
         hu = n;
     }
+    // excess of u as last seen: loaded once, then taken from the returning
+    // subtraction of what u pushed (incoming pushes only ever add to it)
+    int64_t eu = 0;
+    if (gl == 0) eu = ld<SC>(&g.e[u]);
+    eu = __shfl(eu, 0, G);
     for (int cyc = 0; cyc < kc && hu < n; ++cyc) {
-        int64_t eu = 0;
-        if (gl == 0) eu = ld<SC>(&g.e[u]);
-        eu = __shfl(eu, 0, G);
         if (eu <= 0) break;
         if (gl == 0) tl.pr_cyc++;
         int hmin = INT32_MAX;
@@ -514,9 +521,10 @@ __device__ int discharge_group(const DevGraph &g, int u, int kc, const RoundCtx 
             for (int base = beg; base < end && sent < eu; base += G) {
                 const int a = base + gl;
                 int64_t c = 0;
-                int v = -1;
+                int v = -1, tw = 0;
                 if (a < end) {
                     const int2 r = g.arc[a];
+                    tw = g.twin[a];
                     if (r.y > 0 && g.h[r.x] == hmin) {
                         c = max(0, ld<SC>(cf_ptr(g.arc, a)));
                         v = r.x;
@@ -533,13 +541,15 @@ __device__ int discharge_group(const DevGraph &g, int u, int kc, const RoundCtx 
                 const int64_t excl = incl - c;
                 const int64_t d = (c > 0 && excl < room) ? min(c, room - excl) : 0;
                 if (d > 0) {
-                    push_arc<SC>(g, rc, a, v, (int32_t)d, to_t, tl);
+                    push_arc<SC>(g, rc, a, tw, v, (int32_t)d, to_t, tl);
                     tl.push++;
                 }
                 const int64_t tot = min(__shfl(incl, G - 1, G), room);
                 sent += tot;
             }
-            if (gl == 0 && sent) add<SC>(&g.e[u], -sent);
+            int64_t now = eu - sent;
+            if (gl == 0 && sent) now = fetch_add<SC>(&g.e[u], -sent) - sent;
+            eu = __shfl(now, 0, G);
         } else {
             int hn = 0;
             if (gl == 0) {
@@ -551,7 +561,7 @@ __device__ int discharge_group(const DevGraph &g, int u, int kc, const RoundCtx 
             relabels++;
         }
     }
-    if (gl == 0 && hu < n && ld<SC>(&g.e[u]) > 0) list_add<SC>(g, rc, u);
+    if (gl == 0 && hu < n && eu > 0) list_add<SC>(g, rc, u);
     return gl == 0 ? relabels : 0;
 }
 
