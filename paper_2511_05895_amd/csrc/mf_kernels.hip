@@ -427,10 +427,12 @@ __device__ __forceinline__ void list_add(const DevGraph &g, const RoundCtx &rc, 
 }
 
 // First relabel of u in this phase: remember u for RemoveInvalidEdges.  Only
-// the one lane (or wavefront) visiting u in a round touches rmark[u].
+// the one lane (or group) visiting u in a round touches rmark[u]; `stamp` is
+// its value as read at the start of the visit.
 template <int SC>
-__device__ __forceinline__ void note_relabel(const DevGraph &g, int u, int32_t phase_id) {
-    if (g.rmark[u] != phase_id) {
+__device__ __forceinline__ void note_relabel(const DevGraph &g, int u, int32_t phase_id, int32_t &stamp) {
+    if (stamp != phase_id) {
+        stamp = phase_id;
         g.rmark[u] = phase_id;
         const int slot = fetch_add<SC>(&g.ctrl->nrelab, 1);
         g.relab[slot] = u;
@@ -491,6 +493,7 @@ __device__ int discharge_group(const DevGraph &g, int u, int kc, const RoundCtx 
     const int n = g.n;
     const int beg = g.row_ptr[u], end = g.row_ptr[u + 1];
     int hu = g.h[u];
+    int32_t stamp = g.rmark[u];  // phase of u's last first-relabel (read with the rest)
     int relabels = 0;
     if (rc.use_gap && hu < n && hu > ld<SC>(&g.ctrl->gap)) {  // above a gap: cut off
         if (gl == 0) {
@@ -517,7 +520,7 @@ __device__ int discharge_group(const DevGraph &g, int u, int kc, const RoundCtx 
         for (int d = G / 2; d >= 1; d >>= 1) hmin = min(hmin, __shfl_xor(hmin, d, G));
         if (hmin == INT32_MAX) break;
         if (hu > hmin) {
-            int64_t sent = 0;
+            int64_t sent = 0, now = eu;
             for (int base = beg; base < end && sent < eu; base += G) {
                 const int a = base + gl;
                 int64_t c = 0;
@@ -540,22 +543,23 @@ __device__ int discharge_group(const DevGraph &g, int u, int kc, const RoundCtx 
                 const int64_t room = eu - sent;
                 const int64_t excl = incl - c;
                 const int64_t d = (c > 0 && excl < room) ? min(c, room - excl) : 0;
+                const int64_t tot = min(__shfl(incl, G - 1, G), room);
+                // the group's total leaves u before its lanes push it on, so
+                // the returning subtraction overlaps the pushes
+                if (gl == 0 && tot > 0) now = fetch_add<SC>(&g.e[u], -tot) - tot;
                 if (d > 0) {
                     push_arc<SC>(g, rc, a, tw, v, (int32_t)d, to_t, tl);
                     tl.push++;
                 }
-                const int64_t tot = min(__shfl(incl, G - 1, G), room);
                 sent += tot;
             }
-            int64_t now = eu - sent;
-            if (gl == 0 && sent) now = fetch_add<SC>(&g.e[u], -sent) - sent;
             eu = __shfl(now, 0, G);
         } else {
             int hn = 0;
             if (gl == 0) {
                 hn = relabel_to<SC>(g, u, hu, hmin, rc.use_gap);
                 tl.relabel++;
-                note_relabel<SC>(g, u, rc.phase_id);
+                note_relabel<SC>(g, u, rc.phase_id, stamp);
             }
             hu = __shfl(hn, 0, G);
             relabels++;
@@ -894,20 +898,23 @@ __device__ void solve_loop(const DevGraph &g, const Team &tm, const LoopParams &
         int last_change = 0;
         for (;; ++r) {
             const int rd = r % 3, wr = (r + 1) % 3, rs = (r + 2) % 3;
-            const int nl = uniform(ld<SC>(&c->lst[rd].light));
-            const int nh = uniform(ld<SC>(&c->lst[rd].heavy));
+            // the round's control words, read together before any decision
+            const int64_t lh = uniform(ld<SC>(reinterpret_cast<const int64_t *>(&c->lst[rd])));
+            const int64_t prl = uniform(ld<SC>(&c->phase_relabels));
+            const int64_t dl = uniform(ld<SC>(&c->phase_deliv));
+            const int nl = (int)(uint32_t)lh;
+            const int nh = (int)((uint64_t)lh >> 32);
             if (nl + nh == 0) break;
             if (r >= round_cap) {
                 reason = 1;
                 break;
             }
-            if (uniform(ld<SC>(&c->phase_relabels)) > budget) {
+            if (prl > budget) {
                 reason = 2;
                 break;
             }
             // all values read here were written before the last barrier, so
             // every workgroup takes the same decision
-            const int64_t dl = uniform(ld<SC>(&c->phase_deliv));
             if (dl != last_deliv) {
                 last_deliv = dl;
                 last_change = r;
