@@ -334,8 +334,12 @@ MF_API int mf_create(const mf_csr_t *g, const int32_t *cap, int32_t s, int32_t t
 
     // heavy vertices (arc lists handled by a wavefront in topology-driven sweeps)
     std::vector<int32_t> heavy;
-    for (int32_t v = 0; v < n; ++v)
-        if (v != s && v != t && hp.row_ptr[v + 1] - hp.row_ptr[v] > mf::kLightMaxDeg) heavy.push_back(v);
+    int64_t nhuge = 0;  // vertices visited by a whole workgroup
+    for (int32_t v = 0; v < n; ++v) {
+        const int32_t deg = hp.row_ptr[v + 1] - hp.row_ptr[v];
+        if (v != s && v != t && deg > mf::kLightMaxDeg) heavy.push_back(v);
+        if (v != s && v != t && deg > mf::kHugeDeg) nhuge++;
+    }
 
     mf::DevGraph &d = h->g;
     d.n = n;
@@ -365,6 +369,9 @@ MF_API int mf_create(const mf_csr_t *g, const int32_t *cap, int32_t s, int32_t t
     ALLOC(d.list[0], n);
     ALLOC(d.list[1], n);
     ALLOC(d.list[2], n);
+    ALLOC(d.huge[0], nhuge);
+    ALLOC(d.huge[1], nhuge);
+    ALLOC(d.huge[2], nhuge);
     ALLOC(d.mark, n);
     ALLOC(d.rmark, n);
     ALLOC(d.relab, n);
@@ -537,6 +544,7 @@ MF_API int64_t mf_estimate_device_bytes(int32_t n, int64_t m) {
     b += (8 + 4) * (int64_t)n;            // e, h
     b += 2 * 8 * qcap;                    // frontier items
     b += (3 + 3) * 4 * (int64_t)n;        // lists, mark, rmark, relab
+    b += 3 * 4 * (A / mf::kHugeDeg + 1);  // huge-vertex lists
     b += 4 * ((int64_t)n + 1);            // hcount
     b += 4 * (int64_t)n;                  // heavy vertices (at most n)
     b += (int64_t)n;                      // cut side

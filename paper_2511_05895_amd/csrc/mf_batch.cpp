@@ -297,7 +297,8 @@ MF_API int mf_batch_create(int32_t count, const int32_t *n, const int64_t *m, co
     std::vector<mf::HostPairs> hp(count);
     std::vector<int32_t> lim(count);
     int64_t roff = 0, eoff = 0;
-    int64_t sum_n = 0, sum_a = 0, sum_m = 0, sum_q = 0;
+    int64_t sum_n = 0, sum_a = 0, sum_m = 0, sum_q = 0, sum_huge = 0;
+    std::vector<int64_t> nhuge(count, 0);
     for (int32_t i = 0; i < count; ++i) {
         const int64_t *rp = row_ptr + roff;
         const int32_t *ci = (m[i] > 0 && col) ? col + eoff : nullptr;
@@ -324,6 +325,9 @@ MF_API int mf_batch_create(int32_t count, const int32_t *n, const int64_t *m, co
         sum_a += hp[i].A;
         sum_m += m[i];
         sum_q += (int64_t)n[i] + hp[i].A / mf::kChunk + 64;
+        for (int32_t v = 0; v < n[i]; ++v)
+            if (v != s[i] && v != t[i] && hp[i].row_ptr[v + 1] - hp[i].row_ptr[v] > mf::kHugeDeg) nhuge[i]++;
+        sum_huge += nhuge[i];
     }
     if (sum_a >= (int64_t)INT32_MAX * 8) return bfail(nullptr, MF_EINVAL, "batch too large");
 
@@ -356,7 +360,7 @@ MF_API int mf_batch_create(int32_t count, const int32_t *n, const int64_t *m, co
 
     // packed arrays
     int32_t *row_ptr_d, *twin_d, *cap_d, *edge2arc_d, *ecap_d, *stamp_d, *h_d, *l0, *l1, *l2, *mark_d,
-        *rmark_d, *relab_d, *hcount_d;
+        *rmark_d, *relab_d, *hcount_d, *u0, *u1, *u2;
     int2 *arc_d, *q0, *q1;
     int64_t *e_d;
     mf::Ctrl *ctrl_d;
@@ -379,6 +383,9 @@ MF_API int mf_batch_create(int32_t count, const int32_t *n, const int64_t *m, co
     BALLOC(l0, sum_n);
     BALLOC(l1, sum_n);
     BALLOC(l2, sum_n);
+    BALLOC(u0, sum_huge);
+    BALLOC(u1, sum_huge);
+    BALLOC(u2, sum_huge);
     BALLOC(mark_d, sum_n);
     BALLOC(rmark_d, sum_n);
     BALLOC(relab_d, sum_n);
@@ -396,7 +403,7 @@ MF_API int mf_batch_create(int32_t count, const int32_t *n, const int64_t *m, co
     b->values.assign(count, 0);
     b->status.assign(count, 0);
     std::vector<int2> arc_h;
-    int64_t vo = 0, ao = 0, mo = 0, qo = 0, ro = 0;
+    int64_t vo = 0, ao = 0, mo = 0, qo = 0, ro = 0, uo = 0;
     eoff = 0;
     for (int32_t i = 0; i < count; ++i) {
         const mf::HostPairs &p = hp[i];
@@ -421,6 +428,9 @@ MF_API int mf_batch_create(int32_t count, const int32_t *n, const int64_t *m, co
         d.list[0] = l0 + vo;
         d.list[1] = l1 + vo;
         d.list[2] = l2 + vo;
+        d.huge[0] = u0 + uo;
+        d.huge[1] = u1 + uo;
+        d.huge[2] = u2 + uo;
         d.mark = mark_d + vo;
         d.rmark = rmark_d + vo;
         d.relab = relab_d + vo;
@@ -449,6 +459,7 @@ MF_API int mf_batch_create(int32_t count, const int32_t *n, const int64_t *m, co
         mo += m[i];
         eoff += m[i];
         qo += d.qcap;
+        uo += nhuge[i];
     }
     hp.clear();
     if ((e = hipMemcpy(b->d_graphs, b->g.data(), sizeof(mf::DevGraph) * count, hipMemcpyHostToDevice)) !=

@@ -10,6 +10,8 @@ namespace mf {
 // A vertex whose arc list is at most this long is handled by one lane in the
 // push/relabel and invalid-edge sweeps; longer lists get a whole wavefront.
 constexpr int kLightMaxDeg = 32;
+// A vertex with more arcs than this is visited by a whole workgroup.
+constexpr int kHugeDeg = 4096;
 // Arcs per BFS frontier item: a frontier vertex with a longer list is split
 // into several items so that hubs are expanded by many wavefronts at once.
 constexpr int kChunk = 256;
@@ -74,15 +76,18 @@ struct alignas(128) PaddedU32 {
 };
 
 // One active-vertex list of the push/relabel rounds: vertices with short arc
-// lists fill items[0, light) from the front, the others items[n-heavy, n) from
-// the back; `grab` hands out the long-list vertices to wavefronts.  The BFS
-// reserves {light, heavy} together as one 64-bit counter (light in the low
-// half).
-struct alignas(16) ListCtr {
+// lists fill items[0, light) from the front, long ones items[n-heavy, n) from
+// the back, and huge ones (more than kHugeDeg arcs) a list of their own;
+// `grab` hands out the long-list vertices to wavefronts, `hgrab` the huge ones
+// to workgroups.  The BFS reserves {light, heavy} together as one 64-bit
+// counter (light in the low half).
+struct alignas(32) ListCtr {
     int32_t light;
     int32_t heavy;
+    int32_t huge;
     int32_t grab;
-    int32_t pad;
+    int32_t hgrab;
+    int32_t pad[3];
 };
 
 // Device control block: barrier words on their own cache lines, then loop
@@ -133,6 +138,7 @@ struct DevGraph {
     int2 *q[2];         // BFS frontier items {vertex, first arc}, double-buffered
     int64_t qcap;       // items per frontier buffer
     int32_t *list[3];   // n each: active lists of the push/relabel rounds
+    int32_t *huge[3];   // active vertices with more than kHugeDeg arcs, per list
     int32_t *mark;      // n: id of the round list a vertex was last added to
     int32_t *rmark;     // n: id of the phase a vertex last relabelled in
     int32_t *relab;     // n: vertices relabelled in the current phase

@@ -92,6 +92,15 @@ __device__ __forceinline__ int wave_incl_scan(int x) {
     return x;
 }
 
+__device__ __forceinline__ int64_t wave_incl_scan64(int64_t x) {
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int64_t y = __shfl_up(x, d, 64);
+        if (lane_id() >= d) x += y;
+    }
+    return x;
+}
+
 __device__ __forceinline__ int64_t wave_sum(int64_t x) {
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, 64);
@@ -365,7 +374,8 @@ __device__ void bfs_level(const DevGraph &g, const Team &tm, int L, int cnt, boo
             const int cincl = wave_incl_scan(c);
             const int ctotal = __shfl(cincl, 63, 64);
             const bool light = active && vdeg <= kLightMaxDeg;
-            const bool heavy = active && vdeg > kLightMaxDeg;
+            const bool heavy = active && vdeg > kLightMaxDeg && vdeg <= kHugeDeg;
+            const bool huge = active && vdeg > kHugeDeg;
             const uint64_t lm = __ballot(light), hm = __ballot(heavy);
             int qbase = 0;
             int64_t lbase = 0;
@@ -382,6 +392,8 @@ __device__ void bfs_level(const DevGraph &g, const Team &tm, int L, int cnt, boo
                 qout[qb + k] = make_int2(vbeg + k * kChunk, min(vbeg + (k + 1) * kChunk, vend));
             if (light) g.list[0][(int)(uint32_t)lbase + mask_rank(lm)] = v;
             if (heavy) g.list[0][n - 1 - ((int)(lbase >> 32) + mask_rank(hm))] = v;
+            const int su = wave_append1<SC>(&g.ctrl->lst[0].huge, huge);  // rare: hubs only
+            if (huge) g.huge[0][su] = v;
         }
     }
 }
@@ -406,6 +418,7 @@ __device__ void bfs_level(const DevGraph &g, const Team &tm, int L, int cnt, boo
 
 struct RoundCtx {
     int32_t *next;     // list of the next round
+    int32_t *next_huge;  // its huge-vertex list
     ListCtr *next_ctr;
     int32_t next_id;   // round id stamped into mark[] for that list
     int32_t phase_id;  // stamped into rmark[] on a vertex's first relabel
@@ -420,9 +433,12 @@ __device__ __forceinline__ void list_add(const DevGraph &g, const RoundCtx &rc, 
     if (deg <= kLightMaxDeg) {
         const int slot = fetch_add<SC>(&rc.next_ctr->light, 1);
         rc.next[slot] = v;
-    } else {
+    } else if (deg <= kHugeDeg) {
         const int slot = fetch_add<SC>(&rc.next_ctr->heavy, 1);
         rc.next[g.n - 1 - slot] = v;
+    } else {
+        const int slot = fetch_add<SC>(&rc.next_ctr->huge, 1);
+        rc.next_huge[slot] = v;
     }
 }
 
@@ -569,6 +585,107 @@ __device__ int discharge_group(const DevGraph &g, int u, int kc, const RoundCtx 
     return gl == 0 ? relabels : 0;
 }
 
+// A whole workgroup visits vertex u (more than kHugeDeg arcs): the same
+// visit as discharge_group, with the minimum and the push prefix sums taken
+// over the workgroup (wavefront partials in LDS).  Every thread of the
+// workgroup calls it with the same u; all decisions are uniform.
+template <int SC>
+__device__ int discharge_block(const DevGraph &g, int u, int kc, const RoundCtx &rc, Tally &tl,
+                               int64_t &to_t) {
+    __shared__ int s_min[32];
+    __shared__ int64_t s_sum[32];
+    __shared__ int64_t s_now;
+    __shared__ int s_h;
+    const int t = threadIdx.x, lane = lane_id(), w = t >> 6, nw = blockDim.x >> 6;
+    const int n = g.n;
+    const int beg = g.row_ptr[u], end = g.row_ptr[u + 1];
+    int hu = g.h[u];
+    int32_t stamp = g.rmark[u];
+    int relabels = 0;
+    if (rc.use_gap && hu < n && hu > ld<SC>(&g.ctrl->gap)) {  // above a gap: cut off
+        if (t == 0) {
+            add<SC>(&g.hcount[hu], -1);
+            g.h[u] = n;
+        }
+        hu = n;
+    }
+    if (t == 0) s_now = ld<SC>(&g.e[u]);
+    __syncthreads();
+    int64_t eu = s_now;
+    for (int cyc = 0; cyc < kc && hu < n; ++cyc) {
+        if (eu <= 0) break;
+        if (t == 0) tl.pr_cyc++;
+        int hmin = INT32_MAX;
+        for (int a = beg + t; a < end; a += blockDim.x) {
+            const int2 r = g.arc[a];
+            if (r.y > 0) hmin = min(hmin, g.h[r.x]);
+        }
+        if (t == 0) tl.pr_a += end - beg;
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) hmin = min(hmin, __shfl_xor(hmin, d, 64));
+        if (lane == 0) s_min[w] = hmin;
+        __syncthreads();
+        hmin = INT32_MAX;
+        for (int k = 0; k < nw; ++k) hmin = min(hmin, s_min[k]);
+        __syncthreads();
+        if (hmin == INT32_MAX) break;
+        if (hu > hmin) {
+            int64_t sent = 0, now = eu;
+            for (int base = beg; base < end && sent < eu; base += blockDim.x) {
+                const int a = base + t;
+                int64_t c = 0;
+                int v = -1, tw = 0;
+                if (a < end) {
+                    const int2 r = g.arc[a];
+                    tw = g.twin[a];
+                    if (r.y > 0 && g.h[r.x] == hmin) {
+                        c = max(0, ld<SC>(cf_ptr(g.arc, a)));
+                        v = r.x;
+                    }
+                }
+                // inclusive prefix sum of c over the workgroup, in arc order
+                int64_t incl = wave_incl_scan64(c);
+                if (lane == 63) s_sum[w] = incl;
+                __syncthreads();
+                int64_t off = 0, total = 0;
+                for (int k = 0; k < nw; ++k) {
+                    const int64_t x = s_sum[k];
+                    if (k < w) off += x;
+                    total += x;
+                }
+                __syncthreads();
+                incl += off;
+                const int64_t room = eu - sent;
+                const int64_t excl = incl - c;
+                const int64_t d = (c > 0 && excl < room) ? min(c, room - excl) : 0;
+                const int64_t tot = min(total, room);
+                if (t == 0 && tot > 0) now = fetch_add<SC>(&g.e[u], -tot) - tot;
+                if (d > 0) {
+                    push_arc<SC>(g, rc, a, tw, v, (int32_t)d, to_t, tl);
+                    tl.push++;
+                }
+                sent += tot;
+            }
+            if (t == 0) s_now = now;
+            __syncthreads();
+            eu = s_now;
+            __syncthreads();
+        } else {
+            if (t == 0) {
+                s_h = relabel_to<SC>(g, u, hu, hmin, rc.use_gap);
+                tl.relabel++;
+                note_relabel<SC>(g, u, rc.phase_id, stamp);
+            }
+            __syncthreads();
+            hu = s_h;
+            __syncthreads();
+            relabels++;
+        }
+    }
+    if (t == 0 && hu < n && eu > 0) list_add<SC>(g, rc, u);
+    return t == 0 ? relabels : 0;
+}
+
 // Lanes per vertex with a short arc list (at most kLightMaxDeg arcs): the
 // arcs of a typical vertex load in one step instead of one after another.
 constexpr int kLightGroup = 8;
@@ -598,7 +715,7 @@ __device__ __forceinline__ void flush_relabels(Ctrl *c, int64_t &rl, int64_t pus
 // One data-driven round over list rd: short lists by lane, long ones by
 // wavefronts that take the next vertex from a shared counter.
 template <int SC>
-__device__ void pr_round(const DevGraph &g, const Team &tm, int rd, int nl, int nh, int kc,
+__device__ void pr_round(const DevGraph &g, const Team &tm, int rd, int nl, int nh, int nu, int kc,
                          const RoundCtx &rc, Tally &tl) {
     const int64_t gtid = tm.tid();
     const int64_t stride = tm.nthreads();
@@ -612,6 +729,20 @@ __device__ void pr_round(const DevGraph &g, const Team &tm, int rd, int nl, int 
             rl += discharge_group<SC, kLightGroup>(g, i < nl ? lst[i] : -1, kc, rc, tl, to_t);
     }
     flush_to_t<SC>(g, to_t);
+    // huge arc lists: one workgroup per vertex, handed out by a counter
+    if (nu > 0) {
+        __shared__ int s_idx;
+        const int32_t *hl = g.huge[rd];
+        for (;;) {
+            if (threadIdx.x == 0) s_idx = fetch_add<SC>(&g.ctrl->lst[rd].hgrab, 1);
+            __syncthreads();
+            const int idx = s_idx;
+            __syncthreads();
+            if (idx >= nu) break;
+            rl += discharge_block<SC>(g, hl[idx], kc, rc, tl, to_t);
+        }
+        flush_to_t<SC>(g, to_t);
+    }
     int32_t *grab = &g.ctrl->lst[rd].grab;
     for (; nh > 0;) {
         int idx = 0;
@@ -751,7 +882,7 @@ __device__ int policy_decide(const DevGraph &g, const LoopParams &p, Ctrl *c, in
     int64_t reached = 0;
     for (int l = lane; l <= L; l += 64) reached += ld<SC>(&g.hcount[l]);
     reached = wave_sum(reached);
-    const int cnt = ld<SC>(&c->lst[0].light) + ld<SC>(&c->lst[0].heavy);
+    const int cnt = ld<SC>(&c->lst[0].light) + ld<SC>(&c->lst[0].heavy) + ld<SC>(&c->lst[0].huge);
     const int64_t es = ld<SC>(&c->feat_esum);
     float x[F];
     x[0] = log2f((float)(1 + cnt)) / 24.f;
@@ -835,7 +966,7 @@ __device__ void solve_loop(const DevGraph &g, const Team &tm, const LoopParams &
         }
         // --- global relabel ---
         if (leader) {
-            for (int k = 0; k < 3; ++k) c->lst[k] = ListCtr{0, 0, 0, 0};
+            for (int k = 0; k < 3; ++k) c->lst[k] = ListCtr{};
             c->prev_pushes = c->phase_pushes;
             c->prev_relabels = c->phase_relabels;
             c->feat_esum = 0;
@@ -868,7 +999,8 @@ __device__ void solve_loop(const DevGraph &g, const Team &tm, const LoopParams &
         {
             const int nl = uniform(ld<SC>(&c->lst[0].light));
             const int nh = uniform(ld<SC>(&c->lst[0].heavy));
-            if (nl + nh == 0) {
+            const int nu = uniform(ld<SC>(&c->lst[0].huge));
+            if (nl + nh + nu == 0) {
                 if (leader) c->status = kSolved;
                 break;
             }
@@ -892,7 +1024,8 @@ __device__ void solve_loop(const DevGraph &g, const Team &tm, const LoopParams &
                                               : (act_stall(act) == 0 ? 0 : max(1, max(p.stall_rounds, L) * act_stall(act) / 2));
         // --- push/relabel rounds ---
         const int32_t rbase = p.seq_base + uniform(ld<SC>(&c->rounds));
-        const int active0 = uniform(ld<SC>(&c->lst[0].light) + ld<SC>(&c->lst[0].heavy));
+        const int active0 =
+            uniform(ld<SC>(&c->lst[0].light) + ld<SC>(&c->lst[0].heavy) + ld<SC>(&c->lst[0].huge));
         int r = 0, reason = 0;
         int64_t last_deliv = -1;
         int last_change = 0;
@@ -900,11 +1033,12 @@ __device__ void solve_loop(const DevGraph &g, const Team &tm, const LoopParams &
             const int rd = r % 3, wr = (r + 1) % 3, rs = (r + 2) % 3;
             // the round's control words, read together before any decision
             const int64_t lh = uniform(ld<SC>(reinterpret_cast<const int64_t *>(&c->lst[rd])));
+            const int nu = uniform(ld<SC>(&c->lst[rd].huge));
             const int64_t prl = uniform(ld<SC>(&c->phase_relabels));
             const int64_t dl = uniform(ld<SC>(&c->phase_deliv));
             const int nl = (int)(uint32_t)lh;
             const int nh = (int)((uint64_t)lh >> 32);
-            if (nl + nh == 0) break;
+            if (nl + nh + nu == 0) break;
             if (r >= round_cap) {
                 reason = 1;
                 break;
@@ -923,10 +1057,10 @@ __device__ void solve_loop(const DevGraph &g, const Team &tm, const LoopParams &
                 reason = 3;
                 break;
             }
-            if (leader) c->lst[rs] = ListCtr{0, 0, 0, 0};
-            const RoundCtx rc{g.list[wr], &c->lst[wr], rbase + r + 1, rbase, p.use_gap != 0};
+            if (leader) c->lst[rs] = ListCtr{};
+            const RoundCtx rc{g.list[wr], g.huge[wr], &c->lst[wr], rbase + r + 1, rbase, p.use_gap != 0};
             if (topology) pr_round_topology<SC>(g, tm, p.kc, rc, tl);
-            else pr_round<SC>(g, tm, rd, nl, nh, p.kc, rc, tl);
+            else pr_round<SC>(g, tm, rd, nl, nh, nu, p.kc, rc, tl);
             if (!grid_barrier(c, tm, bar_epoch, p.barrier_ticks)) return;
         }
         // --- RemoveInvalidEdges over the vertices that relabelled ---

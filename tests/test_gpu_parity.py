@@ -297,6 +297,39 @@ def test_hubs_long_lists(mf):
             check_solved(F, g, cap)
 
 
+def test_huge_hubs_visited_by_workgroups(mf):
+    """Two inner hubs with about 7000 arcs each (above the workgroup-visit
+    threshold of 4096) besides hub s and hub t: static solve and an update,
+    with one workgroup, a cooperative grid, topology mode, and inside a batch
+    with 256- and 1024-thread workgroups."""
+    rng = np.random.default_rng(12)
+    n = 14000
+    h1, h2 = 5, 6
+    edges = [(0, v, int(rng.integers(1, 40))) for v in range(7, n)]
+    edges += [(v, 1, int(rng.integers(1, 40))) for v in range(7, n, 3)]
+    edges += [(v, h1, int(rng.integers(1, 60))) for v in range(8, n, 3)]
+    edges += [(h1, v, int(rng.integers(1, 60))) for v in range(9, n, 3)]
+    edges += [(v, h2, int(rng.integers(1, 60))) for v in range(9, n, 3)]
+    edges += [(h2, v, int(rng.integers(1, 60))) for v in range(7, n, 3)]
+    edges += [(h1, h2, 500), (h2, h1, 500)]
+    g = from_edges(n, edges, 0, 1)
+    deg = np.diff(g.row_ptr) + np.bincount(g.col, minlength=n)
+    assert deg[h1] > 4096 and deg[h2] > 4096
+    cap2 = None
+    for grid, mode in ((1, 0), (16, 0), (16, 1)):
+        with mf.MaxFlow(g, grid_blocks=grid, mode=mode) as F:
+            F.solve()
+            check_solved(F, g, g.cap)
+            ids, new = W.mixed_batch(g.cap, 3000, 50, np.random.default_rng(grid + mode))
+            cap2 = W.apply_batch(g.cap, ids, new)
+            F.update(ids, new)
+            check_solved(F, g, cap2)
+    for block in (256, 1024):
+        with mf.Batch([g, g], caps=[g.cap, cap2], n_classes=1, block=[block] * 4) as B:
+            vals = B.solve()
+            assert vals[0] == O.dinic(g, g.cap)[0] and vals[1] == O.dinic(g, cap2)[0]
+
+
 def test_repeat_runs_identical_value_and_cut(mf):
     g = W.seg_grid(128, seed=11)
     value, side, _ = O.dinic(g)
