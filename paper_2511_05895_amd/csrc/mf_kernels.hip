@@ -149,6 +149,13 @@ __device__ __forceinline__ int wave_appendn(int32_t *counter, int c) {
 
 __device__ __forceinline__ int n_items(int deg) { return (deg + kChunk - 1) / kChunk; }
 
+// Appends of a round to the next round's list are staged per workgroup in
+// LDS (up to kStageCap light and kStageCap long-list vertices) and reserved
+// with one atomic per workgroup and list at the end of the round; beyond
+// that, or without a stage, a lane appends on its own.  A vertex enters a
+// list at most once (mark[]), so no list outgrows its |V| slots.
+constexpr int kStageCap = 1024;
+
 // A value every lane of the wavefront holds alike (read after a barrier),
 // moved to a scalar register so it does not occupy a vector register.
 __device__ __forceinline__ int32_t uniform(int32_t x) { return __builtin_amdgcn_readfirstlane(x); }
@@ -419,6 +426,9 @@ __device__ void bfs_level(const DevGraph &g, const Team &tm, int L, int cnt, boo
 struct RoundCtx {
     int32_t *next;     // list of the next round
     int32_t *next_huge;  // its huge-vertex list
+    // the workgroup's staging of next-round appends (LDS; null: append directly)
+    int32_t *lbuf, *hbuf;
+    int32_t *lcnt, *hcnt;
     ListCtr *next_ctr;
     int32_t next_id;   // round id stamped into mark[] for that list
     int32_t phase_id;  // stamped into rmark[] on a vertex's first relabel
@@ -431,11 +441,21 @@ __device__ __forceinline__ void list_add(const DevGraph &g, const RoundCtx &rc, 
     const int deg = g.row_ptr[v + 1] - g.row_ptr[v];  // read alongside the exchange
     if (xchg<SC>(&g.mark[v], rc.next_id) == rc.next_id) return;
     if (deg <= kLightMaxDeg) {
-        const int slot = fetch_add<SC>(&rc.next_ctr->light, 1);
-        rc.next[slot] = v;
+        const int k = rc.lbuf ? atomicAdd(rc.lcnt, 1) : kStageCap;
+        if (k < kStageCap) {
+            rc.lbuf[k] = v;
+        } else {
+            const int slot = fetch_add<SC>(&rc.next_ctr->light, 1);
+            rc.next[slot] = v;
+        }
     } else if (deg <= kHugeDeg) {
-        const int slot = fetch_add<SC>(&rc.next_ctr->heavy, 1);
-        rc.next[g.n - 1 - slot] = v;
+        const int k = rc.hbuf ? atomicAdd(rc.hcnt, 1) : kStageCap;
+        if (k < kStageCap) {
+            rc.hbuf[k] = v;
+        } else {
+            const int slot = fetch_add<SC>(&rc.next_ctr->heavy, 1);
+            rc.next[g.n - 1 - slot] = v;
+        }
     } else {
         const int slot = fetch_add<SC>(&rc.next_ctr->huge, 1);
         rc.next_huge[slot] = v;
@@ -712,13 +732,38 @@ __device__ __forceinline__ void flush_relabels(Ctrl *c, int64_t &rl, int64_t pus
     rl = 0;
 }
 
+// Copy the workgroup's staged appends into the next round's list: one
+// reservation per list and workgroup.  Every thread of the workgroup calls it.
+template <int SC>
+__device__ void flush_stage(const DevGraph &g, const RoundCtx &rc) {
+    __shared__ int s_lb, s_hb;
+    __syncthreads();
+    const int nl = min(*rc.lcnt, kStageCap), nh = min(*rc.hcnt, kStageCap);
+    if (threadIdx.x == 0) {
+        s_lb = nl ? fetch_add<SC>(&rc.next_ctr->light, nl) : 0;
+        s_hb = nh ? fetch_add<SC>(&rc.next_ctr->heavy, nh) : 0;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < nl; i += blockDim.x) rc.next[s_lb + i] = rc.lbuf[i];
+    for (int i = threadIdx.x; i < nh; i += blockDim.x) rc.next[g.n - 1 - (s_hb + i)] = rc.hbuf[i];
+}
+
 // One data-driven round over list rd: short lists by lane, long ones by
 // wavefronts that take the next vertex from a shared counter.
 template <int SC>
 __device__ void pr_round(const DevGraph &g, const Team &tm, int rd, int nl, int nh, int nu, int kc,
-                         const RoundCtx &rc, Tally &tl) {
+                         const RoundCtx &rc0, Tally &tl) {
     const int64_t gtid = tm.tid();
     const int64_t stride = tm.nthreads();
+    __shared__ int32_t s_lbuf[kStageCap], s_hbuf[kStageCap];
+    __shared__ int32_t s_lcnt, s_hcnt;
+    if (threadIdx.x == 0) s_lcnt = s_hcnt = 0;
+    __syncthreads();
+    RoundCtx rc = rc0;
+    rc.lbuf = s_lbuf;
+    rc.hbuf = s_hbuf;
+    rc.lcnt = &s_lcnt;
+    rc.hcnt = &s_hcnt;
     const int32_t *lst = g.list[rd];
     int64_t to_t = 0, rl = 0;
     const uint32_t push0 = tl.push;
@@ -754,6 +799,7 @@ __device__ void pr_round(const DevGraph &g, const Team &tm, int rd, int nl, int 
     flush_to_t<SC>(g, to_t);
     flush_relabels<SC>(g.ctrl, rl, (int64_t)(tl.push - push0), tl.deliv);
     tl.deliv = 0;
+    flush_stage<SC>(g, rc);
 }
 
 // One topology-driven round: every vertex is visited (idle when inactive).
@@ -1058,7 +1104,8 @@ __device__ void solve_loop(const DevGraph &g, const Team &tm, const LoopParams &
                 break;
             }
             if (leader) c->lst[rs] = ListCtr{};
-            const RoundCtx rc{g.list[wr], g.huge[wr], &c->lst[wr], rbase + r + 1, rbase, p.use_gap != 0};
+            const RoundCtx rc{g.list[wr], g.huge[wr], nullptr, nullptr, nullptr, nullptr, &c->lst[wr], rbase + r + 1,
+                              rbase, p.use_gap != 0};
             if (topology) pr_round_topology<SC>(g, tm, p.kc, rc, tl);
             else pr_round<SC>(g, tm, rd, nl, nh, nu, p.kc, rc, tl);
             if (!grid_barrier(c, tm, bar_epoch, p.barrier_ticks)) return;
