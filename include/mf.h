@@ -229,6 +229,16 @@ MF_API int mf_export_graph(mf_handle_t *h, int32_t *row_ptr, int32_t *col, int32
 MF_API int mf_export_state(mf_handle_t *h, int32_t *cap, int32_t *cf, int64_t *e,
                            int32_t *height, int32_t *ecap);
 
+/* Restore a residual state exported by mf_export_state from a handle of the
+ * same graph (cap, cf: int32[A]; e: int64[n]; ecap: int32[m]; host arrays,
+ * read during the call).  Checks residuals and capacities for signs and every
+ * arc pair's residuals against its capacities; MF_EINVAL otherwise.  The
+ * handle is left partial: mf_apply_updates* continue from the restored
+ * state, mf_resume finishes it (the value is available after either).  Used
+ * to replay one update from one state under different schedules. */
+MF_API int mf_import_state(mf_handle_t *h, const int32_t *cap, const int32_t *cf, const int64_t *e,
+                           const int32_t *ecap);
+
 /* Per-phase trace of the last solving call.  A phase is the work between two
  * global relabels (Alg. 1/4 loop): one record of 8 int32 per phase, in order,
  * {BFS levels of the global relabel that opened it, active vertices it found,
@@ -375,6 +385,10 @@ MF_API int mf_batch_set_capacities(mf_batch_t *b, int32_t i, const int64_t *edge
 #define MF_POLICY_EXPLORE 2  /* a uniformly drawn action with probability
                                 `explore`, else action 0 (training data)       */
 #define MF_POLICY_FORCED 3   /* `action` in every phase                        */
+#define MF_POLICY_PER_CALL 16 /* OR-ed into a mode: decide at the first phase of
+                                each solving call only and keep that action for
+                                the call's later phases (the learned mode's
+                                value then predicts the whole call's time)     */
 
 typedef struct mf_policy mf_policy_t;
 

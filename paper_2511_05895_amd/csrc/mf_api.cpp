@@ -56,6 +56,7 @@ struct mf_handle {
     float policy_explore = 0.f;
     uint64_t policy_seed = 0;
     int32_t policy_action = 0;
+    int32_t policy_per_call = 0;
     float *d_ptrace = nullptr;
     float batch_fraction = 1.f;  // of the current call
     int32_t epoch = 0;
@@ -157,6 +158,7 @@ int run_loop_and_finish(mf_handle_t *h) {
     p.policy_seed = h->policy_seed;
     p.policy_action = h->policy_action;
     p.batch_fraction = h->batch_fraction;
+    p.policy_per_call = h->policy_per_call;
     // height counts of the gap heuristic start at zero (the loop clears them
     // again before every later global relabel)
     HIP_TRY(h, mf::launch_fill_i32(h->g.hcount, (int64_t)h->g.n + 1, 0, h->stream));
@@ -605,6 +607,38 @@ MF_API int mf_export_state(mf_handle_t *h, int32_t *cap, int32_t *cf, int64_t *e
     return MF_OK;
 }
 
+MF_API int mf_import_state(mf_handle_t *h, const int32_t *cap, const int32_t *cf, const int64_t *e,
+                           const int32_t *ecap) {
+    if (!h) return fail(nullptr, MF_EINVAL, "null handle");
+    if (!e || (h->g.A && (!cap || !cf)) || (h->g.m && !ecap)) return fail(h, MF_EINVAL, "null state arrays");
+    HIP_TRY(h, hipSetDevice(h->device));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    const mf::DevGraph &d = h->g;
+    std::vector<int2> arc((size_t)d.A);
+    std::vector<int32_t> twin((size_t)d.A);
+    if (d.A) {
+        HIP_TRY(h, hipMemcpy(arc.data(), d.arc, sizeof(int2) * d.A, hipMemcpyDeviceToHost));
+        HIP_TRY(h, hipMemcpy(twin.data(), d.twin, sizeof(int32_t) * d.A, hipMemcpyDeviceToHost));
+    }
+    for (int64_t a = 0; a < d.A; ++a) {
+        if (cap[a] < 0 || cf[a] < 0) return fail(h, MF_EINVAL, "negative capacity or residual");
+        const int64_t b = twin[a];
+        if ((int64_t)cf[a] + cf[b] != (int64_t)cap[a] + cap[b])
+            return fail(h, MF_EINVAL, "residuals of an arc pair do not sum to its capacities");
+    }
+    for (int64_t i = 0; i < d.m; ++i)
+        if (ecap[i] < 0 || ecap[i] > h->cap_limit) return fail(h, MF_EINVAL, "edge capacity out of range");
+    for (int64_t a = 0; a < d.A; ++a) arc[a].y = cf[a];
+    if (d.A) {
+        HIP_TRY(h, hipMemcpy(d.arc, arc.data(), sizeof(int2) * d.A, hipMemcpyHostToDevice));
+        HIP_TRY(h, hipMemcpy(d.cap, cap, sizeof(int32_t) * d.A, hipMemcpyHostToDevice));
+    }
+    HIP_TRY(h, hipMemcpy(d.e, e, sizeof(int64_t) * d.n, hipMemcpyHostToDevice));
+    if (d.m) HIP_TRY(h, hipMemcpy(d.ecap, ecap, sizeof(int32_t) * d.m, hipMemcpyHostToDevice));
+    h->state = State::Partial;
+    return MF_OK;
+}
+
 MF_API int mf_get_trace(const mf_handle_t *h, int32_t *out, int32_t max_phases, int32_t *n_out) {
     if (!h || (max_phases > 0 && !out) || max_phases < 0)
         return fail(const_cast<mf_handle_t *>(h), MF_EINVAL, "bad trace arguments");
@@ -619,6 +653,8 @@ MF_API int mf_get_trace(const mf_handle_t *h, int32_t *out, int32_t max_phases, 
 MF_API int mf_set_policy(mf_handle_t *h, const mf_policy_t *policy, int32_t mode, float margin, float explore,
                          uint64_t seed, int32_t action) {
     if (!h) return fail(nullptr, MF_EINVAL, "null handle");
+    const int32_t per_call = (mode & MF_POLICY_PER_CALL) ? 1 : 0;
+    mode &= ~MF_POLICY_PER_CALL;
     if (mode < MF_POLICY_FIXED || mode > MF_POLICY_FORCED) return fail(h, MF_EINVAL, "unknown policy mode");
     if (mode == MF_POLICY_LEARNED && !policy) return fail(h, MF_EINVAL, "the learned mode needs a policy");
     if (policy && mf::policy_device(policy) != h->device)
@@ -642,6 +678,7 @@ MF_API int mf_set_policy(mf_handle_t *h, const mf_policy_t *policy, int32_t mode
     h->policy_explore = explore;
     h->policy_seed = seed;
     h->policy_action = action;
+    h->policy_per_call = mode == MF_POLICY_FIXED ? 0 : per_call;
     return MF_OK;
 }
 

@@ -169,6 +169,8 @@ struct LoopParams {
     uint64_t policy_seed;      // explore: counter-based draws keyed by (seed, seq_base, phase)
     int32_t policy_action;     // forced: the action of every phase
     float batch_fraction;      // edges of the update batch / m (1 for a static solve)
+    int32_t policy_per_call;   // 1: the action of a call's first phase holds for all its phases
+    int32_t pad3_;
 };
 
 // Result of one instance of a batched solve.

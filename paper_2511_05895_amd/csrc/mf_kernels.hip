@@ -942,7 +942,9 @@ __device__ int policy_decide(const DevGraph &g, const LoopParams &p, Ctrl *c, in
     x[14] = log2f((float)(1 + iter)) / 8.f;
     x[15] = p.batch_fraction;
     int act = 0;
-    if (p.policy_mode == kPolicyLearned) {
+    if (p.policy_per_call && iter > 0) {
+        act = ld<SC>(&c->action);  // the call's first decision holds
+    } else if (p.policy_mode == kPolicyLearned) {
         const float *W = p.policy_w;
         const int j = lane & (H - 1);
         float z = W[ob1 + j];

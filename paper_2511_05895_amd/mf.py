@@ -102,6 +102,7 @@ _SIGS = {
     "mf_export_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                   C.c_void_p]),
     "mf_get_trace": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(C.c_int32)]),
+    "mf_import_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "mf_set_stream": (C.c_int, [C.c_void_p, C.c_void_p]),
     "mf_batch_default_opts": (None, [C.POINTER(mf_batch_opts_t)]),
     "mf_batch_create": (C.c_int, [C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
@@ -296,6 +297,14 @@ def mf_export_state(h, n: int, m: int):
     return cap[:A], cf[:A], e, hgt, ecap[:m]
 
 
+def mf_import_state(h, cap, cf, e, ecap):
+    cap = np.ascontiguousarray(cap, dtype=np.int32)
+    cf = np.ascontiguousarray(cf, dtype=np.int32)
+    e = np.ascontiguousarray(e, dtype=np.int64)
+    ecap = np.ascontiguousarray(ecap, dtype=np.int32)
+    return _check(lib().mf_import_state(h, _ptr(cap), _ptr(cf), _ptr(e), _ptr(ecap)), h)
+
+
 TRACE_FIELDS = ("levels", "active", "rounds", "reason", "relabels", "relabelled", "pushes", "last_delivery")
 
 
@@ -398,6 +407,9 @@ class MaxFlow:
 
     def export_state(self):
         return mf_export_state(self.h, self.n, self.m)
+
+    def import_state(self, cap, cf, e, ecap):
+        mf_import_state(self.h, cap, cf, e, ecap)
 
     @property
     def num_arcs(self) -> int:
@@ -603,6 +615,7 @@ class Batch:
 
 POLICY_FEATURES, POLICY_HIDDEN, POLICY_ACTIONS = 16, 32, 8
 MF_POLICY_FIXED, MF_POLICY_LEARNED, MF_POLICY_EXPLORE, MF_POLICY_FORCED = range(4)
+MF_POLICY_PER_CALL = 16
 
 
 def _pcheck(rc):
