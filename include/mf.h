@@ -75,7 +75,7 @@ typedef struct {
     int32_t max_rounds;     /* push/relabel rounds between two global relabels;
                                0 = 65536                                     */
     int32_t relabel_budget; /* relabels allowed between two global relabels
-                               before the next one is forced; 0 = max(1024, n/2) */
+                               before the next one is forced; 0 = max(1024, n/16) */
     int32_t rounds_per_level; /* a phase also ends after this many rounds per
                                level of the BFS that began it (+16); 0 = 1,
                                < 0 = no such cap                             */

@@ -312,7 +312,7 @@ MF_API int mf_create(const mf_csr_t *g, const int32_t *cap, int32_t s, int32_t t
     h->max_iter = o.max_iterations;
     const int64_t budget_ms = o.time_budget_ms > 0 ? o.time_budget_ms : 60000;
     h->max_rounds = o.max_rounds > 0 ? o.max_rounds : 65536;
-    h->relabel_budget = o.relabel_budget > 0 ? o.relabel_budget : std::max<int64_t>(1024, n / 2);
+    h->relabel_budget = o.relabel_budget > 0 ? o.relabel_budget : std::max<int64_t>(1024, n / 16);
     h->rounds_per_level = o.rounds_per_level == 0 ? 1 : (o.rounds_per_level < 0 ? 0 : o.rounds_per_level);
     h->use_gap = (o.flags & MF_FLAG_GAP) ? 1 : 0;
     h->stall_rounds = o.stall_rounds == 0 ? 3 : (o.stall_rounds < 0 ? 0 : o.stall_rounds);

@@ -481,7 +481,7 @@ MF_API int mf_batch_create(int32_t count, const int32_t *n, const int64_t *m, co
     pr.max_iter = -1;
     pr.deadline_ticks = budget_ms * (int64_t)clock_khz;
     pr.barrier_ticks = 10000 * (int64_t)clock_khz;
-    pr.relabel_budget = 0;  // per instance: max(1024, n/2)
+    pr.relabel_budget = 0;  // per instance: max(1024, n/16)
     pr.max_rounds = 65536;
     pr.seq_base = 1;
     pr.rounds_per_level = 1;

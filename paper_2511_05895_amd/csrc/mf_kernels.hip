@@ -1370,7 +1370,7 @@ __global__ void __launch_bounds__(BLOCK)
     __syncthreads();
     LoopParams q = p;
     q.kc = kc[i];
-    if (q.relabel_budget <= 0) q.relabel_budget = max((int64_t)1024, (int64_t)g.n / 2);
+    if (q.relabel_budget <= 0) q.relabel_budget = max((int64_t)1024, (int64_t)g.n / 16);
     solve_loop<kGroup>(g, tm, q);
     __syncthreads();
     if (threadIdx.x == 0) {
