@@ -61,8 +61,10 @@ typedef struct {
 
 typedef struct {
     int32_t kernel_cycles;  /* KERNELCYCLES of Alg. 2: push/relabel attempts per
-                               active vertex per sweep; 0 = max(1, round(m/n)),
-                               the average degree used in Sec. 6.1          */
+                               active vertex per visit; 0 = 1 (Sec. 6.1 uses
+                               the average degree, round(m/n); with rounds a
+                               vertex that keeps excess is visited again in
+                               the next round)                               */
     int32_t mode;           /* MF_MODE_DATA (default) or MF_MODE_TOPOLOGY     */
     int32_t grid_blocks;    /* workgroups of the persistent solve kernel;
                                0 = chosen from the graph size; 1 = one

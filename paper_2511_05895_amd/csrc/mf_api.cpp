@@ -316,8 +316,9 @@ MF_API int mf_create(const mf_csr_t *g, const int32_t *cap, int32_t s, int32_t t
     h->rounds_per_level = o.rounds_per_level == 0 ? 1 : (o.rounds_per_level < 0 ? 0 : o.rounds_per_level);
     h->use_gap = (o.flags & MF_FLAG_GAP) ? 1 : 0;
     h->stall_rounds = o.stall_rounds == 0 ? 3 : (o.stall_rounds < 0 ? 0 : o.stall_rounds);
-    h->kc = o.kernel_cycles > 0 ? o.kernel_cycles
-                                : (int32_t)std::max<int64_t>(1, (int64_t)((double)m / n + 0.5));
+    // one cycle per visit: rounds re-queue a vertex that keeps excess, so
+    // further cycles in one visit mostly repeat what the next round does
+    h->kc = o.kernel_cycles > 0 ? o.kernel_cycles : 1;
     auto bail = [&](int code, const std::string &msg) {
         release(h);
         delete h;
