@@ -88,7 +88,12 @@ typedef struct {
                                (exact labels bring excess that only moves
                                downhill to a root within L rounds);
                                0 = 3, < 0 = no such rule                     */
-    int32_t reserved[2];    /* must be zero                                   */
+    int32_t solo_items;     /* a BFS level whose frontier holds at most this
+                               many items (arc ranges of up to 256 arcs) is
+                               expanded by one workgroup alone, with
+                               workgroup barriers between its levels, while
+                               the others wait; 0 = 128, < 0 = never          */
+    int32_t reserved[1];    /* must be zero                                   */
 } mf_opts_t;
 
 /* opts.flags: turn the gap heuristic on (Sec. 2.2 names gap relabelling as a

@@ -47,6 +47,7 @@ struct mf_handle {
     int32_t rounds_per_level = 1;
     int32_t use_gap = 0;
     int32_t stall_rounds = 3;
+    int32_t solo_items = 0;
     double tick_ms = 1e-5;  // one wall-clock tick in ms
     int32_t seq = 1;  // next round id; round ids stamp mark[] and rmark[]
     // learned phase schedule (mf_set_policy)
@@ -68,6 +69,9 @@ struct mf_handle {
 };
 
 namespace {
+
+// Default frontier size (items) up to which one workgroup runs BFS levels alone.
+constexpr int32_t kSoloItems = 128;
 
 int fail(mf_handle_t *h, int code, const std::string &msg) {
     if (h) h->err = msg;
@@ -151,6 +155,7 @@ int run_loop_and_finish(mf_handle_t *h) {
     p.rounds_per_level = h->rounds_per_level;
     p.use_gap = h->use_gap;
     p.stall_rounds = h->stall_rounds;
+    p.solo_items = h->solo_items;
     p.policy_mode = h->policy_mode;
     p.policy_w = mf::policy_device_params(h->policy);
     p.policy_margin = h->policy_margin;
@@ -252,8 +257,7 @@ bool opts_valid(const mf_opts_t &o, std::string *why) {
     if (o.max_rounds < 0) { *why = "max_rounds must be >= 0"; return false; }
     if (o.relabel_budget < 0) { *why = "relabel_budget must be >= 0"; return false; }
     if (o.flags & ~MF_FLAG_GAP) { *why = "unknown flags"; return false; }
-    for (int i = 0; i < 2; ++i)
-        if (o.reserved[i]) { *why = "reserved fields must be zero"; return false; }
+    if (o.reserved[0]) { *why = "reserved fields must be zero"; return false; }
     return true;
 }
 
@@ -316,6 +320,7 @@ MF_API int mf_create(const mf_csr_t *g, const int32_t *cap, int32_t s, int32_t t
     h->rounds_per_level = o.rounds_per_level == 0 ? 1 : (o.rounds_per_level < 0 ? 0 : o.rounds_per_level);
     h->use_gap = (o.flags & MF_FLAG_GAP) ? 1 : 0;
     h->stall_rounds = o.stall_rounds == 0 ? 3 : (o.stall_rounds < 0 ? 0 : o.stall_rounds);
+    h->solo_items = o.solo_items == 0 ? kSoloItems : (o.solo_items < 0 ? 0 : o.solo_items);
     // one cycle per visit: rounds re-queue a vertex that keeps excess, so
     // further cycles in one visit mostly repeat what the next round does
     h->kc = o.kernel_cycles > 0 ? o.kernel_cycles : 1;

@@ -102,7 +102,7 @@ struct Ctrl {
     int32_t err;        // update validation: 1 id range, 2 capacity range, 4 duplicate
     int32_t stop;       // set by the leader when the time budget ran out
     int32_t rounds;     // push/relabel rounds run by this call (round ids)
-    int32_t pad_;
+    int32_t solo_level; // BFS level reached by a stretch one workgroup ran alone
     int64_t phase_relabels;  // relabels of the current phase
     int64_t phase_pushes;    // pushes of the current phase
     int64_t phase_deliv;     // excess delivered into t or deficient vertices this phase
@@ -111,7 +111,7 @@ struct Ctrl {
     int64_t feat_esum;       // excess of the active vertices found by this phase's BFS
     int32_t feat_hist[8];    // their count per bin of floor(log2 e) / 4 (last bin open)
     int32_t action;          // phase action chosen by the schedule
-    int32_t pad2_;
+    int32_t feat_reached;    // vertices this phase's BFS reached (roots included)
     int64_t prev_pushes;     // pushes and relabels of the previous phase of the call
     int64_t prev_relabels;
     int32_t trace[kTraceCap][kTraceFields];
@@ -170,7 +170,8 @@ struct LoopParams {
     int32_t policy_action;     // forced: the action of every phase
     float batch_fraction;      // edges of the update batch / m (1 for a static solve)
     int32_t policy_per_call;   // 1: the action of a call's first phase holds for all its phases
-    int32_t pad3_;
+    int32_t solo_items;        // a BFS level with at most this many frontier items runs on one
+                               // workgroup alone (workgroup barriers); 0 = never
 };
 
 // Result of one instance of a batched solve.

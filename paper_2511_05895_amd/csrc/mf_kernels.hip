@@ -259,7 +259,7 @@ __device__ void flush_tally(Ctrl *c, Tally &t) {
 // Height reset: t and every deficient vertex other than s are roots (height
 // 0); all others get |V|.  Roots become the level-0 frontier.
 template <int SC>
-__device__ void bfs_roots(const DevGraph &g, const Team &tm, Tally &tl) {
+__device__ void bfs_roots(const DevGraph &g, const Team &tm, bool counts, bool feats, Tally &tl) {
     const int64_t gtid = tm.tid();
     const int64_t stride = tm.nthreads();
     const int64_t nr = ((int64_t)g.n + 63) & ~63ll;
@@ -277,7 +277,8 @@ __device__ void bfs_roots(const DevGraph &g, const Team &tm, Tally &tl) {
         }
         const int c = root ? n_items(end - beg) : 0;
         const int nroot = (int)wave_sum((int64_t)root);
-        if (lane_id() == 0 && nroot) add<SC>(&g.hcount[0], nroot);
+        if (counts && lane_id() == 0 && nroot) add<SC>(&g.hcount[0], nroot);
+        if (feats && lane_id() == 0 && nroot) add<SC>(&g.ctrl->feat_reached, nroot);
         const int base = wave_appendn<SC>(&g.ctrl->qcount[0], c);
         for (int j = 0; j < c; ++j)
             g.q[0][base + j] = make_int2(beg + j * kChunk, min(beg + (j + 1) * kChunk, end));
@@ -300,13 +301,46 @@ __device__ __forceinline__ void feature_tally(Ctrl *c, bool active, int64_t ev) 
     }
 }
 
+// Per-workgroup staging of a large BFS level's output in LDS: frontier items
+// and active-list entries are reserved in LDS first and the workgroup then
+// reserves its whole share of each global list with one atomic, instead of
+// every wavefront step hitting the same few global counters.  A reservation
+// that does not fit goes to the global list directly, so nothing is lost and
+// no slot stays unwritten.
+constexpr int kBfsStageItems = 2048;
+// frontier size (items) from which a level stages its output
+constexpr int kBfsStageMin = 1024;
+struct BfsStage {
+    int2 items[kBfsStageItems];
+    int32_t light[kStageCap], heavy[kStageCap];
+    int32_t cnt[4];  // items, light, heavy, discovered vertices of this level
+    int32_t res[6];  // the level's flush: global bases, then counts, of items, light, heavy
+};
+
+// Reserve k slots of an LDS counter if they fit under cap (no partial
+// reservation); returns the first slot or -1.
+__device__ __forceinline__ int stage_reserve(int32_t *ctr, int k, int cap) {
+    int old = __hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    for (;;) {
+        if (old + k > cap) return -1;
+        if (__hip_atomic_compare_exchange_strong(ctr, &old, old + k, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_WORKGROUP))
+            return old;
+    }
+}
+
 // One BFS level, top-down: for every arc (w -> v) of a frontier item, v joins
 // level L+1 when it is unvisited (height |V|), is not s, and has residual
 // capacity toward w (the twin arc v -> w).  Newly reached vertices become
 // frontier items of the next level; those with positive excess go to the
 // active worklist (A of Alg. 1: e > 0 and h < |V|, s and t excluded).
+// With a stage (st), the level's output is staged per workgroup and flushed
+// at its end; counts: keep the per-height vertex counts (gap heuristic);
+// feats: tally the schedule's features.  Every thread of the workgroup calls
+// it.
 template <int SC>
-__device__ void bfs_level(const DevGraph &g, const Team &tm, int L, int cnt, bool feats, Tally &tl) {
+__device__ void bfs_level(const DevGraph &g, const Team &tm, int L, int cnt, bool feats, bool counts,
+                          BfsStage *st, Tally &tl) {
     const int2 *__restrict__ qin = g.q[L & 1];
     int2 *qout = g.q[(L + 1) & 1];
     int32_t *qout_count = &g.ctrl->qcount[(L + 1) % 3];
@@ -372,11 +406,10 @@ __device__ void bfs_level(const DevGraph &g, const Team &tm, int L, int cnt, boo
             }
             if (feats) feature_tally<SC>(g.ctrl, active, ev);
             const int vdeg = vend - vbeg;
-            const int ndisc = __popcll(__ballot(disc));
-            if (lane == 0 && ndisc) add<SC>(&g.hcount[L + 1], ndisc);
             // reservations of this step: frontier items, and both halves of
             // the active list through one packed 64-bit counter {light, heavy};
             // one lane issues them back to back so their round trips overlap
+            // (or reserves in the workgroup's stage)
             const int c = disc ? n_items(vdeg) : 0;
             const int cincl = wave_incl_scan(c);
             const int ctotal = __shfl(cincl, 63, 64);
@@ -384,25 +417,71 @@ __device__ void bfs_level(const DevGraph &g, const Team &tm, int L, int cnt, boo
             const bool heavy = active && vdeg > kLightMaxDeg && vdeg <= kHugeDeg;
             const bool huge = active && vdeg > kHugeDeg;
             const uint64_t lm = __ballot(light), hm = __ballot(heavy);
-            int qbase = 0;
+            const int ndisc = counts || feats ? __popcll(__ballot(disc)) : 0;
+            int qbase = 0, lsb = -1, hsb = -1, qsb = -1;
             int64_t lbase = 0;
             if (lane == 63) {
-                if (ctotal) qbase = fetch_add<SC>(qout_count, ctotal);
-                if (lm | hm)
+                const int nl = __popcll(lm), nh = __popcll(hm);
+                if (st) {
+                    if (ctotal) qsb = stage_reserve(&st->cnt[0], ctotal, kBfsStageItems);
+                    if (nl) lsb = stage_reserve(&st->cnt[1], nl, kStageCap);
+                    if (nh) hsb = stage_reserve(&st->cnt[2], nh, kStageCap);
+                    if (ndisc) atomicAdd(&st->cnt[3], ndisc);
+                } else if (ndisc) {
+                    if (counts) add<SC>(&g.hcount[L + 1], ndisc);
+                    if (feats) add<SC>(&g.ctrl->feat_reached, ndisc);
+                }
+                if (ctotal && qsb < 0) qbase = fetch_add<SC>(qout_count, ctotal);
+                const int gl = lsb < 0 ? nl : 0, gh = hsb < 0 ? nh : 0;
+                if (gl | gh)
                     lbase = fetch_add<SC>(reinterpret_cast<int64_t *>(&g.ctrl->lst[0]),
-                                          ((int64_t)__popcll(hm) << 32) | (int64_t)__popcll(lm));
+                                          ((int64_t)gh << 32) | (int64_t)gl);
             }
             qbase = __shfl(qbase, 63, 64);
             lbase = __shfl(lbase, 63, 64);
-            const int qb = qbase + cincl - c;
+            qsb = __shfl(qsb, 63, 64);
+            lsb = __shfl(lsb, 63, 64);
+            hsb = __shfl(hsb, 63, 64);
+            int2 *qdst = qsb < 0 ? qout + qbase : st->items + qsb;
+            const int qb = cincl - c;
             for (int k = 0; k < c; ++k)
-                qout[qb + k] = make_int2(vbeg + k * kChunk, min(vbeg + (k + 1) * kChunk, vend));
-            if (light) g.list[0][(int)(uint32_t)lbase + mask_rank(lm)] = v;
-            if (heavy) g.list[0][n - 1 - ((int)(lbase >> 32) + mask_rank(hm))] = v;
+                qdst[qb + k] = make_int2(vbeg + k * kChunk, min(vbeg + (k + 1) * kChunk, vend));
+            if (light) {
+                if (lsb < 0) g.list[0][(int)(uint32_t)lbase + mask_rank(lm)] = v;
+                else st->light[lsb + mask_rank(lm)] = v;
+            }
+            if (heavy) {
+                if (hsb < 0) g.list[0][n - 1 - ((int)(lbase >> 32) + mask_rank(hm))] = v;
+                else st->heavy[hsb + mask_rank(hm)] = v;
+            }
             const int su = wave_append1<SC>(&g.ctrl->lst[0].huge, huge);  // rare: hubs only
             if (huge) g.huge[0][su] = v;
         }
     }
+    if (!st) return;
+    // flush: one reservation per list for the workgroup's staged output, then
+    // a coalesced copy (the stage counters start from zero again)
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int nq = st->cnt[0], nl = st->cnt[1], nh = st->cnt[2], nd = st->cnt[3];
+        int64_t lb = 0;
+        st->res[0] = nq ? fetch_add<SC>(qout_count, nq) : 0;
+        if (nl | nh)
+            lb = fetch_add<SC>(reinterpret_cast<int64_t *>(&g.ctrl->lst[0]), ((int64_t)nh << 32) | (int64_t)nl);
+        if (nd && counts) add<SC>(&g.hcount[L + 1], nd);
+        if (nd && feats) add<SC>(&g.ctrl->feat_reached, nd);
+        st->res[1] = (int)(uint32_t)lb;
+        st->res[2] = (int)(lb >> 32);
+        st->res[3] = nq;
+        st->res[4] = nl;
+        st->res[5] = nh;
+        st->cnt[0] = st->cnt[1] = st->cnt[2] = st->cnt[3] = 0;
+    }
+    __syncthreads();
+    const int nq = st->res[3], nl = st->res[4], nh = st->res[5];
+    for (int i = threadIdx.x; i < nq; i += blockDim.x) qout[st->res[0] + i] = st->items[i];
+    for (int i = threadIdx.x; i < nl; i += blockDim.x) g.list[0][st->res[1] + i] = st->light[i];
+    for (int i = threadIdx.x; i < nh; i += blockDim.x) g.list[0][n - 1 - (st->res[2] + i)] = st->heavy[i];
 }
 
 // ---------------------------------------------------------------------------
@@ -925,9 +1004,7 @@ __device__ int policy_decide(const DevGraph &g, const LoopParams &p, Ctrl *c, in
     constexpr int F = kPolF, H = kPolH, K = kPolK;
     constexpr int oW1 = 0, ob1 = oW1 + H * F, oW2 = ob1 + H, ob2 = oW2 + H * H, oW3 = ob2 + H, ob3 = oW3 + K * H;
     const int lane = lane_id();
-    int64_t reached = 0;
-    for (int l = lane; l <= L; l += 64) reached += ld<SC>(&g.hcount[l]);
-    reached = wave_sum(reached);
+    const int64_t reached = ld<SC>(&c->feat_reached);
     const int cnt = ld<SC>(&c->lst[0].light) + ld<SC>(&c->lst[0].heavy) + ld<SC>(&c->lst[0].huge);
     const int64_t es = ld<SC>(&c->feat_esum);
     float x[F];
@@ -995,7 +1072,7 @@ __device__ int policy_decide(const DevGraph &g, const LoopParams &p, Ctrl *c, in
 // ---------------------------------------------------------------------------
 
 template <int SC>
-__device__ void solve_loop(const DevGraph &g, const Team &tm, const LoopParams &p) {
+__device__ void solve_loop(const DevGraph &g, const Team &tm, const LoopParams &p, BfsStage *stage) {
     Ctrl *c = g.ctrl;
     if (ld<SC>(&c->err)) return;  // update batch rejected: leave the state alone
     Tally tl;
@@ -1004,6 +1081,8 @@ __device__ void solve_loop(const DevGraph &g, const Team &tm, const LoopParams &
     int64_t iter = 0;
     uint32_t bar_epoch = 0;  // barriers this launch has passed
     const bool policy = p.policy_mode != kPolicyFixed;
+    // vertices per height are counted only for the gap heuristic
+    const bool counts = p.use_gap != 0;
     const uint64_t t0 = wall_clock64();
     for (;;) {
         // time budget: the leader raised `stop` before the last barrier, so
@@ -1027,16 +1106,35 @@ __device__ void solve_loop(const DevGraph &g, const Team &tm, const LoopParams &
             add<SC>(&c->stat[kStGlobalRelabels], 1);
         }
         const uint64_t tb = wall_clock64();
-        bfs_roots<SC>(g, tm, tl);
+        bfs_roots<SC>(g, tm, counts, policy, tl);
         if (!grid_barrier(c, tm, bar_epoch, p.barrier_ticks)) return;
         int L = 0;
         for (;;) {
             const int cnt = uniform(ld<SC>(&c->qcount[L % 3]));
             if (cnt == 0) break;
-            if (leader) c->qcount[(L + 2) % 3] = 0;
-            bfs_level<SC>(g, tm, L, cnt, policy, tl);
+            // A small frontier is expanded by the first workgroup alone, level
+            // after level with workgroup barriers in between (no grid barrier,
+            // no L2 invalidation), while the others wait at the next grid
+            // barrier.  The stretch ends at a level with no item or more than
+            // solo_items items, or after a quarter of the barrier's wait limit.
+            const bool alone = tm.size > 1 && cnt <= p.solo_items;
+            if (!alone || tm.rank == 0) {
+                const Team bt = alone ? Team{0, 1} : tm;
+                const uint64_t ts = wall_clock64();
+                for (int k = cnt;;) {
+                    if (threadIdx.x == 0 && tm.rank == 0) c->qcount[(L + 2) % 3] = 0;
+                    bfs_level<SC>(g, bt, L, k, policy, counts, !alone && k >= kBfsStageMin ? stage : nullptr, tl);
+                    if (!alone) break;
+                    __syncthreads();
+                    ++L;
+                    k = uniform(ld<SC>(&c->qcount[L % 3]));
+                    if (k == 0 || k > p.solo_items) break;
+                    if (uniform((int64_t)(wall_clock64() - ts)) > p.barrier_ticks / 4) break;
+                }
+                if (alone && threadIdx.x == 0) c->solo_level = L;
+            }
             if (!grid_barrier(c, tm, bar_epoch, p.barrier_ticks)) return;
-            ++L;
+            L = alone ? uniform(ld<SC>(&c->solo_level)) : L + 1;
         }
         const uint64_t tp = wall_clock64();
         if (leader) {
@@ -1116,7 +1214,8 @@ __device__ void solve_loop(const DevGraph &g, const Team &tm, const LoopParams &
         const uint64_t tr = wall_clock64();
         const int nrel = uniform(ld<SC>(&c->nrelab));
         remove_invalid<SC>(g, tm, g.relab, nrel, p.use_gap != 0, tl);
-        for (int64_t i = tm.tid(); i <= g.n; i += tm.nthreads()) g.hcount[i] = 0;
+        if (counts)
+            for (int64_t i = tm.tid(); i <= g.n; i += tm.nthreads()) g.hcount[i] = 0;
         {
             if (leader && c->ntrace < kTraceCap) {
                 int32_t *tr_rec = c->trace[c->ntrace];
@@ -1139,6 +1238,7 @@ __device__ void solve_loop(const DevGraph &g, const Team &tm, const LoopParams &
             c->qcount[0] = 0;
             c->qcount[1] = 0;
             c->qcount[2] = 0;
+            c->feat_reached = 0;  // counted from the next phase's roots on
             c->rounds += r + 1;
             add<SC>(&c->stat[kStIterations], 1);
             add<SC>(&c->stat[kStRounds], (int64_t)r);
@@ -1171,7 +1271,14 @@ __device__ void solve_loop(const DevGraph &g, const Team &tm, const LoopParams &
 // The whole grid is one team (cooperative launch), or a single workgroup.
 template <int BLOCK, int SC>
 __global__ void __launch_bounds__(BLOCK) k_loop(DevGraph g, LoopParams p) {
-    solve_loop<SC>(g, Team{(int)blockIdx.x, (int)gridDim.x}, p);
+    BfsStage *stage = nullptr;
+    if constexpr (SC == kAgent) {
+        __shared__ BfsStage s_stage;
+        if (threadIdx.x < 4) s_stage.cnt[threadIdx.x] = 0;
+        __syncthreads();
+        stage = &s_stage;
+    }
+    solve_loop<SC>(g, Team{(int)blockIdx.x, (int)gridDim.x}, p, stage);
 }
 
 // ---------------------------------------------------------------------------
@@ -1371,7 +1478,7 @@ __global__ void __launch_bounds__(BLOCK)
     LoopParams q = p;
     q.kc = kc[i];
     if (q.relabel_budget <= 0) q.relabel_budget = max((int64_t)1024, (int64_t)g.n / 16);
-    solve_loop<kGroup>(g, tm, q);
+    solve_loop<kGroup>(g, tm, q, nullptr);
     __syncthreads();
     if (threadIdx.x == 0) {
         BatchResult r;

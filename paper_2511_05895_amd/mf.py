@@ -33,7 +33,8 @@ class mf_opts_t(C.Structure):
     _fields_ = [("kernel_cycles", C.c_int32), ("mode", C.c_int32), ("grid_blocks", C.c_int32),
                 ("device", C.c_int32), ("max_iterations", C.c_int64), ("time_budget_ms", C.c_int32),
                 ("max_rounds", C.c_int32), ("relabel_budget", C.c_int32), ("rounds_per_level", C.c_int32),
-                ("flags", C.c_int32), ("stall_rounds", C.c_int32), ("reserved", C.c_int32 * 2)]
+                ("flags", C.c_int32), ("stall_rounds", C.c_int32), ("solo_items", C.c_int32),
+                ("reserved", C.c_int32 * 1)]
 
 
 class mf_stats_t(C.Structure):
@@ -327,8 +328,9 @@ class MaxFlow:
 
     def __init__(self, g, kernel_cycles=0, mode=MF_MODE_DATA, grid_blocks=0, max_iterations=-1,
                  device=0, cap=None, time_budget_ms=0, max_rounds=0, relabel_budget=0,
-                 rounds_per_level=0, flags=0, stall_rounds=0):
+                 rounds_per_level=0, flags=0, stall_rounds=0, solo_items=0):
         o = mf_default_opts()
+        o.solo_items = solo_items
         o.time_budget_ms = time_budget_ms
         o.max_rounds = max_rounds
         o.relabel_budget = relabel_budget

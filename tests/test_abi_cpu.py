@@ -76,7 +76,7 @@ def test_create_rejects_bad_arguments(case, expect):
         opts.mode = 7
     elif case == "reserved":
         opts = mf.mf_default_opts()
-        opts.reserved[1] = 1
+        opts.reserved[0] = 1
     elif case == "cap limit":
         cap = [5, 1 << 30]
     rc, h, msg = _create(n, rp, col, cap, s, t, opts)
