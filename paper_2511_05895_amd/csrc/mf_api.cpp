@@ -48,6 +48,7 @@ struct mf_handle {
     int32_t use_gap = 0;
     int32_t stall_rounds = 3;
     int32_t solo_items = 0;
+    int32_t combine = 0;
     double tick_ms = 1e-5;  // one wall-clock tick in ms
     int32_t seq = 1;  // next round id; round ids stamp mark[] and rmark[]
     // learned phase schedule (mf_set_policy)
@@ -156,6 +157,7 @@ int run_loop_and_finish(mf_handle_t *h) {
     p.use_gap = h->use_gap;
     p.stall_rounds = h->stall_rounds;
     p.solo_items = h->solo_items;
+    p.combine = h->combine;
     p.policy_mode = h->policy_mode;
     p.policy_w = mf::policy_device_params(h->policy);
     p.policy_margin = h->policy_margin;
@@ -348,6 +350,9 @@ MF_API int mf_create(const mf_csr_t *g, const int32_t *cap, int32_t s, int32_t t
         if (v != s && v != t && deg > mf::kLightMaxDeg) heavy.push_back(v);
         if (v != s && v != t && deg > mf::kHugeDeg) nhuge++;
     }
+    // vertices of huge degree draw pushes from many others at once: add them
+    // up per workgroup first
+    h->combine = nhuge > 0 ? 1 : 0;
 
     mf::DevGraph &d = h->g;
     d.n = n;

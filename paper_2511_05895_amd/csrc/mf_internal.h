@@ -78,16 +78,14 @@ struct alignas(128) PaddedU32 {
 // One active-vertex list of the push/relabel rounds: vertices with short arc
 // lists fill items[0, light) from the front, long ones items[n-heavy, n) from
 // the back, and huge ones (more than kHugeDeg arcs) a list of their own;
-// `grab` hands out the long-list vertices to wavefronts, `hgrab` the huge ones
-// to workgroups.  The BFS reserves {light, heavy} together as one 64-bit
-// counter (light in the low half).
+// `hgrab` hands out the huge ones to workgroups.  The BFS reserves
+// {light, heavy} together as one 64-bit counter (light in the low half).
 struct alignas(32) ListCtr {
     int32_t light;
     int32_t heavy;
     int32_t huge;
-    int32_t grab;
     int32_t hgrab;
-    int32_t pad[3];
+    int32_t pad[4];
 };
 
 // Device control block: barrier words on their own cache lines, then loop
@@ -172,6 +170,9 @@ struct LoopParams {
     int32_t policy_per_call;   // 1: the action of a call's first phase holds for all its phases
     int32_t solo_items;        // a BFS level with at most this many frontier items runs on one
                                // workgroup alone (workgroup barriers); 0 = never
+    int32_t combine;           // 1: a workgroup adds up a round's pushes per target vertex before
+                               // touching its excess (graphs with vertices of huge degree)
+    int32_t pad4_;
 };
 
 // Result of one instance of a batched solve.

@@ -502,12 +502,27 @@ __device__ void bfs_level(const DevGraph &g, const Team &tm, int L, int cnt, boo
 // take exactly these arcs), otherwise it relabels h(u) = h^ + 1.
 // ---------------------------------------------------------------------------
 
+// Per-workgroup sums of a round's pushes by target vertex (LDS, direct
+// mapped): a push into a vertex that holds a slot adds to the slot; the
+// workgroup adds every slot to the target's excess with one atomic at the end
+// of the round.  Pushes whose slot belongs to another vertex go straight to
+// the excess.  Vertices of huge degree take pushes from thousands of others
+// in one round, and this turns them into one atomic per workgroup.
+constexpr int kCombineBits = 9;
+constexpr int kCombine = 1 << kCombineBits;
+struct Combine {
+    int32_t key[kCombine];  // target vertex, or -1
+    int64_t sum[kCombine];
+};
+
 struct RoundCtx {
     int32_t *next;     // list of the next round
     int32_t *next_huge;  // its huge-vertex list
-    // the workgroup's staging of next-round appends (LDS; null: append directly)
-    int32_t *lbuf, *hbuf;
-    int32_t *lcnt, *hcnt;
+    // the workgroup's staging of next-round appends and of first relabels
+    // (LDS; null: append directly)
+    int32_t *lbuf, *hbuf, *rbuf;
+    int32_t *lcnt, *hcnt, *rcnt;
+    Combine *comb;     // push sums of the workgroup (LDS), or null
     ListCtr *next_ctr;
     int32_t next_id;   // round id stamped into mark[] for that list
     int32_t phase_id;  // stamped into rmark[] on a vertex's first relabel
@@ -545,12 +560,17 @@ __device__ __forceinline__ void list_add(const DevGraph &g, const RoundCtx &rc, 
 // the one lane (or group) visiting u in a round touches rmark[u]; `stamp` is
 // its value as read at the start of the visit.
 template <int SC>
-__device__ __forceinline__ void note_relabel(const DevGraph &g, int u, int32_t phase_id, int32_t &stamp) {
-    if (stamp != phase_id) {
-        stamp = phase_id;
-        g.rmark[u] = phase_id;
-        const int slot = fetch_add<SC>(&g.ctrl->nrelab, 1);
-        g.relab[slot] = u;
+__device__ __forceinline__ void note_relabel(const DevGraph &g, const RoundCtx &rc, int u, int32_t &stamp) {
+    if (stamp != rc.phase_id) {
+        stamp = rc.phase_id;
+        g.rmark[u] = rc.phase_id;
+        const int k = rc.rbuf ? atomicAdd(rc.rcnt, 1) : kStageCap;
+        if (k < kStageCap) {
+            rc.rbuf[k] = u;
+        } else {
+            const int slot = fetch_add<SC>(&g.ctrl->nrelab, 1);
+            g.relab[slot] = u;
+        }
     }
 }
 
@@ -587,9 +607,56 @@ __device__ __forceinline__ void push_arc(const DevGraph &g, const RoundCtx &rc, 
     if (v == g.t) {
         to_t += d;
     } else {
+        if (rc.comb) {
+            const int slot = (int)(((uint32_t)v * 2654435761u) >> (32 - kCombineBits));
+            int k = rc.comb->key[slot];
+            if (k < 0) {
+                k = atomicCAS(&rc.comb->key[slot], -1, v);
+                if (k < 0) k = v;
+            }
+            if (k == v) {
+                atomicAdd(reinterpret_cast<unsigned long long *>(&rc.comb->sum[slot]), (unsigned long long)d);
+                return;
+            }
+        }
         const int64_t old = fetch_add<SC>(&g.e[v], (int64_t)d);
         if (old < 0) tl.deliv += min((int64_t)d, -old);  // part of a deficit filled
         if (old <= 0 && old + d > 0 && v != g.s) list_add<SC>(g, rc, v);
+    }
+}
+
+// Lowest residual neighbour height over the arcs first, first + stride, ...
+// below last, and the residual capacity of the arcs at that height; four
+// arcs per lane in flight.
+__device__ __forceinline__ void scan_lowest(const DevGraph &g, int first, int last, int stride, int &hmin,
+                                            int64_t &cmin) {
+    int a = first;
+    for (; a + 3 * stride < last; a += 4 * stride) {
+        int2 r[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) r[k] = g.arc[a + k * stride];
+        int hv[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) hv[k] = r[k].y > 0 ? g.h[r[k].x] : INT32_MAX;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (hv[k] < hmin) {
+                hmin = hv[k];
+                cmin = r[k].y;
+            } else if (hv[k] == hmin) {
+                cmin += r[k].y;
+            }
+        }
+    }
+    for (; a < last; a += stride) {
+        const int2 r = g.arc[a];
+        const int hv = r.y > 0 ? g.h[r.x] : INT32_MAX;
+        if (hv < hmin) {
+            hmin = hv;
+            cmin = r.y;
+        } else if (hv == hmin) {
+            cmin += r.y;
+        }
     }
 }
 
@@ -626,10 +693,8 @@ __device__ int discharge_group(const DevGraph &g, int u, int kc, const RoundCtx 
         if (eu <= 0) break;
         if (gl == 0) tl.pr_cyc++;
         int hmin = INT32_MAX;
-        for (int a = beg + gl; a < end; a += G) {
-            const int2 r = g.arc[a];
-            if (r.y > 0) hmin = min(hmin, g.h[r.x]);
-        }
+        int64_t cmin = 0;  // not needed here
+        scan_lowest(g, beg + gl, end, G, hmin, cmin);
         if (gl == 0) tl.pr_a += end - beg;
 #pragma unroll
         for (int d = G / 2; d >= 1; d >>= 1) hmin = min(hmin, __shfl_xor(hmin, d, G));
@@ -674,7 +739,7 @@ __device__ int discharge_group(const DevGraph &g, int u, int kc, const RoundCtx 
             if (gl == 0) {
                 hn = relabel_to<SC>(g, u, hu, hmin, rc.use_gap);
                 tl.relabel++;
-                note_relabel<SC>(g, u, rc.phase_id, stamp);
+                note_relabel<SC>(g, rc, u, stamp);
             }
             hu = __shfl(hn, 0, G);
             relabels++;
@@ -684,10 +749,16 @@ __device__ int discharge_group(const DevGraph &g, int u, int kc, const RoundCtx 
     return gl == 0 ? relabels : 0;
 }
 
-// A whole workgroup visits vertex u (more than kHugeDeg arcs): the same
-// visit as discharge_group, with the minimum and the push prefix sums taken
-// over the workgroup (wavefront partials in LDS).  Every thread of the
-// workgroup calls it with the same u; all decisions are uniform.
+// A whole workgroup visits vertex u (more than kHugeDeg arcs).  Each
+// wavefront owns a contiguous chunk of u's arcs and finds, in one pass, its
+// lowest residual neighbour height and the residual capacity toward it; the
+// chunks' capacities at the overall lowest height h^ split the excess in arc
+// order, so every wavefront then pushes its share along its own chunk without
+// workgroup barriers.  Without races this makes exactly the pushes of one
+// pass over all arcs in arc order (the same as discharge_group); a capacity
+// or height that changed since the scan only leaves excess behind.  Every
+// thread of the workgroup calls it with the same u; all decisions are
+// uniform.
 template <int SC>
 __device__ int discharge_block(const DevGraph &g, int u, int kc, const RoundCtx &rc, Tally &tl,
                                int64_t &to_t) {
@@ -698,6 +769,8 @@ __device__ int discharge_block(const DevGraph &g, int u, int kc, const RoundCtx 
     const int t = threadIdx.x, lane = lane_id(), w = t >> 6, nw = blockDim.x >> 6;
     const int n = g.n;
     const int beg = g.row_ptr[u], end = g.row_ptr[u + 1];
+    const int chunk = ((end - beg + nw - 1) / nw + 63) & ~63;
+    const int cb = min(end, beg + w * chunk), ce = min(end, cb + chunk);
     int hu = g.h[u];
     int32_t stamp = g.rmark[u];
     int relabels = 0;
@@ -713,28 +786,46 @@ __device__ int discharge_block(const DevGraph &g, int u, int kc, const RoundCtx 
     int64_t eu = s_now;
     for (int cyc = 0; cyc < kc && hu < n; ++cyc) {
         if (eu <= 0) break;
-        if (t == 0) tl.pr_cyc++;
-        int hmin = INT32_MAX;
-        for (int a = beg + t; a < end; a += blockDim.x) {
-            const int2 r = g.arc[a];
-            if (r.y > 0) hmin = min(hmin, g.h[r.x]);
+        if (t == 0) {
+            tl.pr_cyc++;
+            tl.pr_a += end - beg;
         }
-        if (t == 0) tl.pr_a += end - beg;
+        int hm = INT32_MAX;
+        int64_t cm = 0;
+        scan_lowest(g, cb + lane, ce, 64, hm, cm);
 #pragma unroll
-        for (int d = 32; d >= 1; d >>= 1) hmin = min(hmin, __shfl_xor(hmin, d, 64));
-        if (lane == 0) s_min[w] = hmin;
+        for (int d = 32; d >= 1; d >>= 1) {
+            const int oh = __shfl_xor(hm, d, 64);
+            const int64_t oc = __shfl_xor(cm, d, 64);
+            if (oh < hm) {
+                hm = oh;
+                cm = oc;
+            } else if (oh == hm) {
+                cm += oc;
+            }
+        }
+        if (lane == 0) {
+            s_min[w] = hm;
+            s_sum[w] = cm;
+        }
         __syncthreads();
-        hmin = INT32_MAX;
+        int hmin = INT32_MAX;
         for (int k = 0; k < nw; ++k) hmin = min(hmin, s_min[k]);
+        int64_t off = 0;  // capacity at h^ in the chunks before this one
+        for (int k = 0; k < w; ++k)
+            if (s_min[k] == hmin) off += s_sum[k];
+        const int64_t mine = hm == hmin ? cm : 0;
         __syncthreads();
         if (hmin == INT32_MAX) break;
         if (hu > hmin) {
-            int64_t sent = 0, now = eu;
-            for (int base = beg; base < end && sent < eu; base += blockDim.x) {
-                const int a = base + t;
+            // this chunk's part of [0, eu) in arc order
+            const int64_t room = max((int64_t)0, min(mine, eu - off));
+            int64_t sent = 0;
+            for (int base = cb; base < ce && sent < room; base += 64) {
+                const int a = base + lane;
                 int64_t c = 0;
                 int v = -1, tw = 0;
-                if (a < end) {
+                if (a < ce) {
                     const int2 r = g.arc[a];
                     tw = g.twin[a];
                     if (r.y > 0 && g.h[r.x] == hmin) {
@@ -742,38 +833,26 @@ __device__ int discharge_block(const DevGraph &g, int u, int kc, const RoundCtx 
                         v = r.x;
                     }
                 }
-                // inclusive prefix sum of c over the workgroup, in arc order
-                int64_t incl = wave_incl_scan64(c);
-                if (lane == 63) s_sum[w] = incl;
-                __syncthreads();
-                int64_t off = 0, total = 0;
-                for (int k = 0; k < nw; ++k) {
-                    const int64_t x = s_sum[k];
-                    if (k < w) off += x;
-                    total += x;
-                }
-                __syncthreads();
-                incl += off;
-                const int64_t room = eu - sent;
+                const int64_t incl = wave_incl_scan64(c);
+                const int64_t rem = room - sent;
                 const int64_t excl = incl - c;
-                const int64_t d = (c > 0 && excl < room) ? min(c, room - excl) : 0;
-                const int64_t tot = min(total, room);
-                if (t == 0 && tot > 0) now = fetch_add<SC>(&g.e[u], -tot) - tot;
+                const int64_t d = (c > 0 && excl < rem) ? min(c, rem - excl) : 0;
                 if (d > 0) {
                     push_arc<SC>(g, rc, a, tw, v, (int32_t)d, to_t, tl);
                     tl.push++;
                 }
-                sent += tot;
+                sent += min(__shfl(incl, 63, 64), rem);
             }
-            if (t == 0) s_now = now;
+            if (lane == 0 && sent > 0) add<SC>(&g.e[u], -sent);
+            __syncthreads();
+            if (t == 0) s_now = ld<SC>(&g.e[u]);
             __syncthreads();
             eu = s_now;
-            __syncthreads();
         } else {
             if (t == 0) {
                 s_h = relabel_to<SC>(g, u, hu, hmin, rc.use_gap);
                 tl.relabel++;
-                note_relabel<SC>(g, u, rc.phase_id, stamp);
+                note_relabel<SC>(g, rc, u, stamp);
             }
             __syncthreads();
             hu = s_h;
@@ -811,38 +890,70 @@ __device__ __forceinline__ void flush_relabels(Ctrl *c, int64_t &rl, int64_t pus
     rl = 0;
 }
 
-// Copy the workgroup's staged appends into the next round's list: one
-// reservation per list and workgroup.  Every thread of the workgroup calls it.
+// Copy the workgroup's staged appends into the next round's list and the
+// phase's relabelled list: one reservation per list and workgroup; add the workgroup's round counters
+// (acc: excess into t, relabels, pushes, deliveries into deficits).  Every
+// thread of the workgroup calls it.
 template <int SC>
-__device__ void flush_stage(const DevGraph &g, const RoundCtx &rc) {
-    __shared__ int s_lb, s_hb;
+__device__ void flush_stage(const DevGraph &g, const RoundCtx &rc, const int64_t *acc) {
+    __shared__ int s_lb, s_hb, s_rb;
     __syncthreads();
-    const int nl = min(*rc.lcnt, kStageCap), nh = min(*rc.hcnt, kStageCap);
+    const int nl = min(*rc.lcnt, kStageCap), nh = min(*rc.hcnt, kStageCap), nr = min(*rc.rcnt, kStageCap);
     if (threadIdx.x == 0) {
         s_lb = nl ? fetch_add<SC>(&rc.next_ctr->light, nl) : 0;
         s_hb = nh ? fetch_add<SC>(&rc.next_ctr->heavy, nh) : 0;
+        s_rb = nr ? fetch_add<SC>(&g.ctrl->nrelab, nr) : 0;
+        Ctrl *c = g.ctrl;
+        if (acc[0]) add<SC>(&g.e[g.t], acc[0]);
+        if (acc[0] + acc[3]) add<SC>(&c->phase_deliv, acc[0] + acc[3]);
+        if (acc[1]) add<SC>(&c->phase_relabels, acc[1]);
+        if (acc[2]) add<SC>(&c->phase_pushes, acc[2]);
     }
     __syncthreads();
     for (int i = threadIdx.x; i < nl; i += blockDim.x) rc.next[s_lb + i] = rc.lbuf[i];
     for (int i = threadIdx.x; i < nh; i += blockDim.x) rc.next[g.n - 1 - (s_hb + i)] = rc.hbuf[i];
+    for (int i = threadIdx.x; i < nr; i += blockDim.x) g.relab[s_rb + i] = rc.rbuf[i];
+}
+
+// Add the workgroup's push sums to the targets' excess (every thread of the
+// workgroup calls it); a target whose excess turns positive joins the next
+// round's list, as after a single push.
+template <int SC>
+__device__ void flush_combine(const DevGraph &g, const RoundCtx &rc, Tally &tl) {
+    __syncthreads();
+    for (int i = threadIdx.x; i < kCombine; i += blockDim.x) {
+        const int v = rc.comb->key[i];
+        if (v < 0) continue;
+        const int64_t d = rc.comb->sum[i];
+        rc.comb->key[i] = -1;
+        rc.comb->sum[i] = 0;
+        const int64_t old = fetch_add<SC>(&g.e[v], d);
+        if (old < 0) tl.deliv += min(d, -old);
+        if (old <= 0 && old + d > 0 && v != g.s) list_add<SC>(g, rc, v);
+    }
 }
 
 // One data-driven round over list rd: short lists by lane, long ones by
 // wavefronts that take the next vertex from a shared counter.
 template <int SC>
 __device__ void pr_round(const DevGraph &g, const Team &tm, int rd, int nl, int nh, int nu, int kc,
-                         const RoundCtx &rc0, Tally &tl) {
+                         const RoundCtx &rc0, Combine *comb, Tally &tl) {
     const int64_t gtid = tm.tid();
     const int64_t stride = tm.nthreads();
-    __shared__ int32_t s_lbuf[kStageCap], s_hbuf[kStageCap];
-    __shared__ int32_t s_lcnt, s_hcnt;
-    if (threadIdx.x == 0) s_lcnt = s_hcnt = 0;
+    __shared__ int32_t s_lbuf[kStageCap], s_hbuf[kStageCap], s_rbuf[kStageCap];
+    __shared__ int32_t s_lcnt, s_hcnt, s_rcnt;
+    __shared__ int64_t s_acc[4];  // the workgroup's excess into t, relabels, pushes, deliveries
+    if (threadIdx.x == 0) s_lcnt = s_hcnt = s_rcnt = 0;
+    if (threadIdx.x < 4) s_acc[threadIdx.x] = 0;
     __syncthreads();
     RoundCtx rc = rc0;
     rc.lbuf = s_lbuf;
     rc.hbuf = s_hbuf;
+    rc.rbuf = s_rbuf;
     rc.lcnt = &s_lcnt;
     rc.hcnt = &s_hcnt;
+    rc.rcnt = &s_rcnt;
+    rc.comb = comb;
     const int32_t *lst = g.list[rd];
     int64_t to_t = 0, rl = 0;
     const uint32_t push0 = tl.push;
@@ -852,7 +963,6 @@ __device__ void pr_round(const DevGraph &g, const Team &tm, int rd, int nl, int 
         for (int64_t k = 0, i = grp; k < trips; ++k, i += ngrp)
             rl += discharge_group<SC, kLightGroup>(g, i < nl ? lst[i] : -1, kc, rc, tl, to_t);
     }
-    flush_to_t<SC>(g, to_t);
     // huge arc lists: one workgroup per vertex, handed out by a counter
     if (nu > 0) {
         __shared__ int s_idx;
@@ -865,20 +975,22 @@ __device__ void pr_round(const DevGraph &g, const Team &tm, int rd, int nl, int 
             if (idx >= nu) break;
             rl += discharge_block<SC>(g, hl[idx], kc, rc, tl, to_t);
         }
-        flush_to_t<SC>(g, to_t);
     }
-    int32_t *grab = &g.ctrl->lst[rd].grab;
-    for (; nh > 0;) {
-        int idx = 0;
-        if (lane_id() == 0) idx = fetch_add<SC>(grab, 1);
-        idx = __shfl(idx, 0, 64);
-        if (idx >= nh) break;
-        rl += discharge_group<SC, 64>(g, lst[g.n - 1 - idx], kc, rc, tl, to_t);
+    // long arc lists: one wavefront per vertex, dealt out round-robin (no
+    // shared counter for thousands of wavefronts to contend on)
+    for (int64_t i = tm.wave(); i < nh; i += tm.nwaves())
+        rl += discharge_group<SC, 64>(g, lst[g.n - 1 - i], kc, rc, tl, to_t);
+    if (comb) flush_combine<SC>(g, rc, tl);
+    // the round's counters: summed over the workgroup, one atomic each
+    {
+        const int64_t v[4] = {wave_sum(to_t), wave_sum(rl), wave_sum((int64_t)(tl.push - push0)),
+                              wave_sum(tl.deliv)};
+        if (lane_id() == 0)
+            for (int k = 0; k < 4; ++k)
+                if (v[k]) atomicAdd(reinterpret_cast<unsigned long long *>(&s_acc[k]), (unsigned long long)v[k]);
+        tl.deliv = 0;
     }
-    flush_to_t<SC>(g, to_t);
-    flush_relabels<SC>(g.ctrl, rl, (int64_t)(tl.push - push0), tl.deliv);
-    tl.deliv = 0;
-    flush_stage<SC>(g, rc);
+    flush_stage<SC>(g, rc, s_acc);
 }
 
 // One topology-driven round: every vertex is visited (idle when inactive).
@@ -1072,7 +1184,8 @@ __device__ int policy_decide(const DevGraph &g, const LoopParams &p, Ctrl *c, in
 // ---------------------------------------------------------------------------
 
 template <int SC>
-__device__ void solve_loop(const DevGraph &g, const Team &tm, const LoopParams &p, BfsStage *stage) {
+__device__ void solve_loop(const DevGraph &g, const Team &tm, const LoopParams &p, BfsStage *stage,
+                           Combine *comb) {
     Ctrl *c = g.ctrl;
     if (ld<SC>(&c->err)) return;  // update batch rejected: leave the state alone
     Tally tl;
@@ -1204,10 +1317,11 @@ __device__ void solve_loop(const DevGraph &g, const Team &tm, const LoopParams &
                 break;
             }
             if (leader) c->lst[rs] = ListCtr{};
-            const RoundCtx rc{g.list[wr], g.huge[wr], nullptr, nullptr, nullptr, nullptr, &c->lst[wr], rbase + r + 1,
+            const RoundCtx rc{g.list[wr], g.huge[wr], nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, &c->lst[wr],
+                              rbase + r + 1,
                               rbase, p.use_gap != 0};
             if (topology) pr_round_topology<SC>(g, tm, p.kc, rc, tl);
-            else pr_round<SC>(g, tm, rd, nl, nh, nu, p.kc, rc, tl);
+            else pr_round<SC>(g, tm, rd, nl, nh, nu, p.kc, rc, p.combine ? comb : nullptr, tl);
             if (!grid_barrier(c, tm, bar_epoch, p.barrier_ticks)) return;
         }
         // --- RemoveInvalidEdges over the vertices that relabelled ---
@@ -1272,13 +1386,20 @@ __device__ void solve_loop(const DevGraph &g, const Team &tm, const LoopParams &
 template <int BLOCK, int SC>
 __global__ void __launch_bounds__(BLOCK) k_loop(DevGraph g, LoopParams p) {
     BfsStage *stage = nullptr;
+    Combine *comb = nullptr;
     if constexpr (SC == kAgent) {
         __shared__ BfsStage s_stage;
+        __shared__ Combine s_comb;
         if (threadIdx.x < 4) s_stage.cnt[threadIdx.x] = 0;
+        for (int i = threadIdx.x; i < kCombine; i += blockDim.x) {
+            s_comb.key[i] = -1;
+            s_comb.sum[i] = 0;
+        }
         __syncthreads();
         stage = &s_stage;
+        comb = &s_comb;
     }
-    solve_loop<SC>(g, Team{(int)blockIdx.x, (int)gridDim.x}, p, stage);
+    solve_loop<SC>(g, Team{(int)blockIdx.x, (int)gridDim.x}, p, stage, comb);
 }
 
 // ---------------------------------------------------------------------------
@@ -1478,7 +1599,7 @@ __global__ void __launch_bounds__(BLOCK)
     LoopParams q = p;
     q.kc = kc[i];
     if (q.relabel_budget <= 0) q.relabel_budget = max((int64_t)1024, (int64_t)g.n / 16);
-    solve_loop<kGroup>(g, tm, q, nullptr);
+    solve_loop<kGroup>(g, tm, q, nullptr, nullptr);
     __syncthreads();
     if (threadIdx.x == 0) {
         BatchResult r;
