@@ -395,7 +395,10 @@ MF_API int mf_batch_set_capacities(mf_batch_t *b, int32_t i, const int64_t *edge
 #define MF_POLICY_PER_CALL 16 /* OR-ed into a mode: decide at the first phase of
                                 each solving call only and keep that action for
                                 the call's later phases (the learned mode's
-                                value then predicts the whole call's time)     */
+                                value then predicts the whole call's time).
+                                The BFS then tallies x1..x9 and x11 in the
+                                first phase only: later phases' trace records
+                                hold zeros there                              */
 
 typedef struct mf_policy mf_policy_t;
 

@@ -256,7 +256,7 @@ def test_learned_schedule_beats_the_fixed_rule_on_held_out_graphs(mf):
     family and batch size (a shorter relabel budget on grids, longer phases
     on R-MAT at large batches), which one rule cannot serve.  The learned
     per-call schedule must need less loop time than the fixed rule in total
-    (medians of three alternating repetitions per graph), with identical
+    (medians of five alternating repetitions per graph), with identical
     values."""
     train = [W.rmat(16, 16, 900 + i) for i in range(3)] + [W.rmat(17, 16, 903 + i) for i in range(2)]
     train += [W.seg_grid(128, seed=40), W.seg_grid(160, seed=41), W.seg_grid(160, seed=42),
@@ -274,7 +274,7 @@ def test_learned_schedule_beats_the_fixed_rule_on_held_out_graphs(mf):
         evals = [W.rmat(17, 16, 990), W.rmat(18, 16, 991), W.seg_grid(192, seed=70), W.seg_grid(224, seed=71)]
         for gi, g in enumerate(evals):
             tf, tl, acts = [], [], []
-            for rep in range(3):
+            for rep in range(5):
                 t, vf = _chain_time(mf, g, 12, 7 + gi, None)
                 tf.append(t)
                 t, vl = _chain_time(mf, g, 12, 7 + gi, P, acts)
