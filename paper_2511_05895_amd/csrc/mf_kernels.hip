@@ -753,102 +753,6 @@ __device__ int discharge_group(const DevGraph &g, int u, int kc, const RoundCtx 
 // arcs of a typical vertex load in one step instead of one after another.
 constexpr int kLightGroup = 8;
 
-// One visit (one cycle) of a vertex with at most kLightMaxDeg arcs by a
-// group of kLightGroup lanes from a single load of its arcs, twins and head
-// heights: the push pass works on the scan's registers instead of reading
-// them again.  A residual capacity the scan read is a lower bound of the
-// current one (only u's own pushes lower it, and u has one visitor per
-// round), so pushing it never overdraws an arc.  The pushes are the ones
-// discharge_group makes: along the arcs at the lowest height in arc order
-// until the excess is gone, the total leaving u with one returning atomic
-// issued ahead of them.  u < 0: the group idles.
-template <int SC>
-__device__ int discharge_light(const DevGraph &g, int u, const RoundCtx &rc, Tally &tl, int64_t &to_t) {
-    constexpr int G = kLightGroup, S = kLightMaxDeg / kLightGroup;
-    const int gl = lane_id() & (G - 1);
-    if (u < 0) return 0;
-    const int n = g.n;
-    const int beg = g.row_ptr[u], end = g.row_ptr[u + 1];
-    int hu = g.h[u];
-    int32_t stamp = g.rmark[u];
-    int64_t eu = 0;
-    if (gl == 0) eu = ld<SC>(&g.e[u]);
-    eu = __shfl(eu, 0, G);
-    if (rc.use_gap && hu < n && hu > ld<SC>(&g.ctrl->gap)) {  // above a gap: cut off
-        if (gl == 0) {
-            add<SC>(&g.hcount[hu], -1);
-            g.h[u] = n;
-        }
-        hu = n;
-    }
-    if (hu >= n || eu <= 0) return 0;
-    if (gl == 0) {
-        tl.pr_cyc++;
-        tl.pr_a += end - beg;
-    }
-    int2 r[S];
-    int tw[S], hv[S];
-#pragma unroll
-    for (int k = 0; k < S; ++k) {
-        const int a = beg + k * G + gl;
-        r[k] = make_int2(0, 0);
-        tw[k] = 0;
-        if (a < end) {
-            r[k] = g.arc[a];
-            tw[k] = g.twin[a];
-        }
-    }
-    int hmin = INT32_MAX;
-#pragma unroll
-    for (int k = 0; k < S; ++k) {
-        hv[k] = r[k].y > 0 ? g.h[r[k].x] : INT32_MAX;
-        hmin = min(hmin, hv[k]);
-    }
-#pragma unroll
-    for (int d = G / 2; d >= 1; d >>= 1) hmin = min(hmin, __shfl_xor(hmin, d, G));
-    int relabels = 0;
-    if (hmin == INT32_MAX) {
-        // no residual arc: nothing to do this visit
-    } else if (hu > hmin) {
-        int64_t dk[S];
-        int64_t sent = 0;
-#pragma unroll
-        for (int k = 0; k < S; ++k) {
-            const int64_t c = hv[k] == hmin ? (int64_t)r[k].y : 0;
-            int64_t incl = c;
-#pragma unroll
-            for (int d = 1; d < G; d <<= 1) {
-                const int64_t y = __shfl_up(incl, d, G);
-                if (gl >= d) incl += y;
-            }
-            const int64_t room = eu - sent;
-            const int64_t excl = incl - c;
-            dk[k] = (c > 0 && excl < room) ? min(c, room - excl) : 0;
-            sent += min(__shfl(incl, G - 1, G), room);
-        }
-        int64_t now = eu;
-        if (gl == 0 && sent > 0) now = fetch_add<SC>(&g.e[u], -sent) - sent;
-#pragma unroll
-        for (int k = 0; k < S; ++k)
-            if (dk[k] > 0) {
-                push_arc<SC>(g, rc, beg + k * G + gl, tw[k], r[k].x, (int32_t)dk[k], to_t, tl);
-                tl.push++;
-            }
-        eu = __shfl(now, 0, G);
-    } else {
-        int hn = 0;
-        if (gl == 0) {
-            hn = relabel_to<SC>(g, u, hu, hmin, rc.use_gap);
-            tl.relabel++;
-            note_relabel<SC>(g, rc, u, stamp);
-        }
-        hu = __shfl(hn, 0, G);
-        relabels = 1;
-    }
-    if (gl == 0 && hu < n && eu > 0) list_add<SC>(g, rc, u);
-    return gl == 0 ? relabels : 0;
-}
-
 // A whole workgroup visits vertex u (more than kHugeDeg arcs).  Each
 // wavefront owns a contiguous chunk of u's arcs and finds, in one pass, its
 // lowest residual neighbour height and the residual capacity toward it; the
@@ -1056,11 +960,8 @@ __device__ void pr_round(const DevGraph &g, const Team &tm, int rd, int nl, int 
     {
         const int64_t grp = gtid / kLightGroup, ngrp = stride / kLightGroup;
         const int64_t trips = (nl + ngrp - 1) / ngrp;  // the same for every group
-        for (int64_t k = 0, i = grp; k < trips; ++k, i += ngrp) {
-            const int u = i < nl ? lst[i] : -1;
-            rl += kc == 1 ? discharge_light<SC>(g, u, rc, tl, to_t)
-                          : discharge_group<SC, kLightGroup>(g, u, kc, rc, tl, to_t);
-        }
+        for (int64_t k = 0, i = grp; k < trips; ++k, i += ngrp)
+            rl += discharge_group<SC, kLightGroup>(g, i < nl ? lst[i] : -1, kc, rc, tl, to_t);
     }
     // huge arc lists: one workgroup per vertex, handed out by a counter
     if (nu > 0) {
