@@ -415,7 +415,7 @@ def main():
     ap.add_argument("--config", default="grid512", choices=sorted(CONFIGS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
-    ap.add_argument("--grid-blocks", type=int, default=16)
+    ap.add_argument("--grid-blocks", type=int, default=0)  # 0: the library sizes the grid
     ap.add_argument("--kernel-cycles", type=int, default=1)
     ap.add_argument("--mode", type=int, default=0)
     ap.add_argument("--workers", type=int, default=2, help="serving workers (c5)")
