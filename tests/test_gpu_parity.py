@@ -330,6 +330,23 @@ def test_huge_hubs_visited_by_workgroups(mf):
             assert vals[0] == O.dinic(g, g.cap)[0] and vals[1] == O.dinic(g, cap2)[0]
 
 
+@pytest.mark.parametrize("solo", [-1, 1, 128, 1 << 20])
+def test_small_bfs_frontiers_on_one_workgroup(mf, solo):
+    """BFS levels whose frontier holds at most `solo_items` items run on the
+    first workgroup alone (-1: never; 1: single-item levels; 2^20: every
+    level).  Values, cuts, validated states and the exact final heights stay
+    the same, for a static solve and updates."""
+    g = W.seg_grid(128, seed=12)
+    with mf.MaxFlow(g, grid_blocks=8, solo_items=solo) as F:
+        F.solve()
+        check_solved(F, g, g.cap)
+        cap = g.cap.copy()
+        for ids, new in W.batch_chain(g, 0.01, 2, 100, seed=W.SEED_BASE + 12):
+            cap[ids] = new
+            F.update(ids, new)
+            check_solved(F, g, cap)
+
+
 def test_repeat_runs_identical_value_and_cut(mf):
     g = W.seg_grid(128, seed=11)
     value, side, _ = O.dinic(g)
