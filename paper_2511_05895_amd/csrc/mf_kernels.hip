@@ -15,11 +15,14 @@
 //    takes one arc), so a hub's arcs spread over many wavefronts and low-degree
 //    frontiers still fill all 64 lanes.  The active worklist is built during the
 //    same BFS (a discovered vertex with positive excess is active), with
-//    ballot/mbcnt compaction and one atomic per wavefront.
-//  * Push/relabel and invalid-edge removal give one lane to a vertex with at
-//    most kLightMaxDeg arcs and a whole wavefront (packed (height, arc) minimum
-//    reduction) to longer lists.  Excess added to t by one wavefront is summed
-//    before a single atomic.
+//    ballot/mbcnt compaction and one atomic per wavefront, or per workgroup
+//    (LDS staging) on large levels; small frontiers are expanded by one
+//    workgroup alone, level after level, without grid barriers.
+//  * Push/relabel gives a group of lanes to a vertex with at most kLightMaxDeg
+//    arcs, a wavefront to a longer list and a workgroup to a huge one.  Every
+//    counter or list that all workgroups share is updated once per workgroup
+//    and round (LDS sums and staging): atomics on one address serialise, and a
+//    round has thousands of wavefronts.
 //  * Memory ordering: residual capacities and excesses that other lanes may be
 //    changing are read with device-scope atomic loads before a push amount is
 //    fixed, so a push never exceeds the latest residual or excess (only the
@@ -104,15 +107,6 @@ __device__ __forceinline__ int64_t wave_incl_scan64(int64_t x) {
 __device__ __forceinline__ int64_t wave_sum(int64_t x) {
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, 64);
-    return x;
-}
-
-__device__ __forceinline__ uint64_t wave_min(uint64_t x) {
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) {
-        uint64_t y = __shfl_xor(x, d, 64);
-        x = y < x ? y : x;
-    }
     return x;
 }
 
@@ -868,7 +862,8 @@ __device__ int discharge_block(const DevGraph &g, int u, int kc, const RoundCtx 
     return t == 0 ? relabels : 0;
 }
 
-// Excess pushed into t by the lanes of a wavefront, added with one atomic.
+// Excess pushed into t by the lanes of a wavefront, added with one atomic
+// (topology-driven rounds; data-driven rounds sum per workgroup).
 template <int SC>
 __device__ __forceinline__ void flush_to_t(const DevGraph &g, int64_t &to_t) {
     const int64_t s = wave_sum(to_t);
