@@ -46,10 +46,12 @@ BYTES = {
 }
 
 CONFIGS = {
-    "grid512": dict(desc="segmentation grid 512x512, 1% mixed batches", frac=0.01, inc_hi=100),
-    "rmat20": dict(desc="R-MAT scale 20 (avg degree 16), 1% mixed batches", frac=0.01, inc_hi=1000),
-    "random1k": dict(desc="random graph 1,000 V / 8,000 E, 100-edge mixed batches", frac=0.0125,
-                     inc_hi=100),
+    "grid512": dict(desc="segmentation grid 512x512, 1% mixed batches", base="segmentation grid 512x512",
+                    frac=0.01, inc_hi=100),
+    "rmat20": dict(desc="R-MAT scale 20 (avg degree 16), 1% mixed batches", base="R-MAT scale 20 (avg degree 16)",
+                   frac=0.01, inc_hi=1000),
+    "random1k": dict(desc="random graph 1,000 V / 8,000 E, 100-edge mixed batches",
+                     base="random graph 1,000 V / 8,000 E", frac=0.0125, inc_hi=100),
     "c4": dict(desc="256 uneven instances (grids 32^2..256^2, random graphs 1k..50k V at degree 8), "
                     "batched static solve"),
     "c5": dict(desc="R-MAT scale 22 (4,194,304 V / 67,108,864 E) served: requests of 10..100k edges "
@@ -418,6 +420,12 @@ def main():
     ap.add_argument("--grid-blocks", type=int, default=0)  # 0: the library sizes the grid
     ap.add_argument("--kernel-cycles", type=int, default=1)
     ap.add_argument("--mode", type=int, default=0)
+    ap.add_argument("--updates", choices=["mixed", "inc", "dec"], default="mixed",
+                    help="update family: half increments (default), all increments, all decrements")
+    ap.add_argument("--batch-fraction", type=float, default=0.0,
+                    help="edges per batch / m (0: the workload's own, 1%% or 100 edges)")
+    ap.add_argument("--p-st", type=float, default=0.0,
+                    help="probability that a batch edge is drawn from the edges out of s / into t")
     ap.add_argument("--workers", type=int, default=2, help="serving workers (c5)")
     ap.add_argument("--closed-requests", type=int, default=30, help="closed-loop requests (c5)")
     ap.add_argument("--open-requests", type=int, default=100, help="open-loop requests per load (c5)")
@@ -448,10 +456,18 @@ def main():
             torch.neg(src, out=dst)
         torch.cuda.synchronize()
         del src, dst
-    cfg = CONFIGS[args.config]
+    cfg = dict(CONFIGS[args.config])
     g, seed = make_graph(args.config)
     K, Wm = args.steps, args.warmup
-    chain = list(W.batch_chain(g, cfg["frac"], Wm + K, cfg["inc_hi"], seed=seed))
+    inc_fraction = {"mixed": 0.5, "inc": 1.0, "dec": 0.0}[args.updates]
+    if args.batch_fraction > 0 or args.updates != "mixed" or args.p_st > 0:
+        frac = args.batch_fraction if args.batch_fraction > 0 else cfg["frac"]
+        kind = {"mixed": "mixed", "inc": "incremental", "dec": "decremental"}[args.updates]
+        cfg["desc"] = cfg["base"] + f", {frac * 100:g}% {kind} batches" + \
+            (f", s/t bias {args.p_st:g}" if args.p_st > 0 else "")
+        cfg["frac"] = frac
+    chain = list(W.batch_chain(g, cfg["frac"], Wm + K, cfg["inc_hi"], seed=seed,
+                               inc_fraction=inc_fraction, p_st=args.p_st))
     k = int(chain[0][0].shape[0])
     dev_chain = [(torch.from_numpy(i).to(dev), torch.from_numpy(c).to(dev)) for i, c in chain]
     torch.cuda.synchronize()

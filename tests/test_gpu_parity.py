@@ -330,6 +330,32 @@ def test_huge_hubs_visited_by_workgroups(mf):
             assert vals[0] == O.dinic(g, g.cap)[0] and vals[1] == O.dinic(g, cap2)[0]
 
 
+@pytest.mark.parametrize("kind", ["inc", "dec", "mixed"])
+@pytest.mark.parametrize("which", ["grid", "rmat"])
+def test_update_families_with_st_bias(mf, kind, which):
+    """The paper's incremental, decremental and mixed update families, with
+    batch edges drawn from the edges out of s and into t with probability
+    0.3: every update matches the oracle (value, cut, validated state, exact
+    heights), incremental chains never lower the value and decremental ones
+    never raise it."""
+    g = W.seg_grid(128, seed=31) if which == "grid" else W.rmat(15, 16, seed=32)
+    frac = {"inc": 1.0, "dec": 0.0, "mixed": 0.5}[kind]
+    inc = 100 if which == "grid" else 1000
+    with mf.MaxFlow(g) as F:
+        prev = F.solve()
+        check_solved(F, g, g.cap)
+        cap = g.cap.copy()
+        for ids, new in W.batch_chain(g, 0.02, 3, inc, seed=W.SEED_BASE + 33, inc_fraction=frac, p_st=0.3):
+            cap[ids] = new
+            v = F.update(ids, new)
+            check_solved(F, g, cap)
+            if kind == "inc":
+                assert v >= prev
+            elif kind == "dec":
+                assert v <= prev
+            prev = v
+
+
 @pytest.mark.parametrize("solo", [-1, 1, 128, 1 << 20])
 def test_small_bfs_frontiers_on_one_workgroup(mf, solo):
     """BFS levels whose frontier holds at most `solo_items` items run on the

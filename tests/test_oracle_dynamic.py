@@ -219,3 +219,23 @@ def test_validator_rejects_dropped_flow():
     cf[a] -= 1
     cf[pg.twin[a]] += 1
     assert O.validate(pg, cf, p.e)[0] == 3
+
+
+@pytest.mark.parametrize("kind", ["inc", "dec"])
+def test_biased_families_monotone_and_lipschitz_on_a_grid(kind):
+    """The paper's update families with picks biased toward s/t edges: an
+    incremental chain never lowers the value, a decremental one never raises
+    it, and no batch moves it by more than the capacity it changed."""
+    g = W.seg_grid(24, seed=21)
+    p = O.PaperSeq(g)
+    prev = p.solve()
+    cap = g.cap.copy()
+    frac = 1.0 if kind == "inc" else 0.0
+    for ids, new in W.batch_chain(g, 0.05, 4, 100, seed=31, inc_fraction=frac, p_st=0.5):
+        dcap = int(np.abs(new.astype(np.int64) - cap[ids]).sum())
+        cap[ids] = new
+        v = p.update(ids, new)
+        assert v == O.dinic(g, cap)[0]
+        assert (v >= prev) if kind == "inc" else (v <= prev)
+        assert abs(v - prev) <= dcap
+        prev = v

@@ -2,6 +2,7 @@
 import hashlib
 
 import numpy as np
+import pytest
 
 import workloads as W
 
@@ -71,3 +72,61 @@ def test_batches():
         assert np.all(new[50:] <= old[50:]) and np.all(new[50:] >= 0)
         cap[ids] = new
     assert W.batch_size(1570816, 0.01) == 15708
+
+
+# ---------------- update families and the s/t bias ----------------
+
+def test_st_edges_are_the_edges_out_of_s_and_into_t():
+    g = W.seg_grid(16, seed=3)
+    tails = np.repeat(np.arange(g.n), np.diff(g.row_ptr))
+    st = W.st_edges(g)
+    want = [i for i in range(g.m) if tails[i] == g.s or g.col[i] == g.t]
+    assert st.tolist() == want
+    assert st.shape[0] == 2 * 16 * 16  # one t-link each way per pixel
+
+
+@pytest.mark.parametrize("p_st", [0.0, 0.3, 1.0])
+def test_biased_picks_are_distinct_and_seeded(p_st):
+    g = W.seg_grid(32, seed=5)
+    st = W.st_edges(g)
+    a = W.pick_edges(g.m, 500, np.random.default_rng(7), st, p_st)
+    b = W.pick_edges(g.m, 500, np.random.default_rng(7), st, p_st)
+    assert np.array_equal(a, b)
+    assert np.unique(a).shape[0] == 500 and a.min() >= 0 and a.max() < g.m
+    share = np.isin(a, st).mean()
+    if p_st == 1.0:
+        assert share == 1.0
+    elif p_st == 0.0:
+        # unbiased: the s/t share is about their share of all edges (2048 of 6016)
+        assert abs(share - st.shape[0] / g.m) < 0.1
+    else:
+        assert abs(share - p_st) < 0.1
+
+
+def test_bias_capped_by_the_available_edges():
+    g = W.c1_random_1k()
+    st = W.st_edges(g)
+    ids = W.pick_edges(g.m, 100, np.random.default_rng(1), st, 1.0)
+    assert np.unique(ids).shape[0] == 100
+    assert np.isin(ids, st).sum() == st.shape[0]  # every s/t edge, the rest elsewhere
+
+
+def test_unbiased_chain_unchanged_by_the_knob():
+    g = W.c1_random_1k()
+    a = list(W.batch_chain(g, 0.0125, 3, 100, seed=11))
+    b = list(W.batch_chain(g, 0.0125, 3, 100, seed=11, p_st=0.0))
+    for (i0, n0), (i1, n1) in zip(a, b):
+        assert np.array_equal(i0, i1) and np.array_equal(n0, n1)
+
+
+@pytest.mark.parametrize("inc_fraction", [1.0, 0.0])
+def test_update_families_move_capacities_one_way(inc_fraction):
+    g = W.seg_grid(24, seed=9)
+    cur = g.cap.copy()
+    for ids, new in W.batch_chain(g, 0.05, 3, 100, seed=13, inc_fraction=inc_fraction, p_st=0.5):
+        old = cur[ids]
+        if inc_fraction == 1.0:
+            assert (new > old).all()
+        else:
+            assert (new <= old).all() and (new >= 0).all()
+        cur[ids] = new

@@ -194,14 +194,38 @@ def batch_size(m: int, fraction: float) -> int:
     return max(1, int(round(m * fraction)))
 
 
+def st_edges(g: Graph) -> np.ndarray:
+    """Ids of the edges out of the source or into the sink."""
+    tails = np.repeat(np.arange(g.n, dtype=np.int64), np.diff(g.row_ptr))
+    return np.flatnonzero((tails == g.s) | (g.col == g.t)).astype(np.int64)
+
+
+def pick_edges(m: int, k: int, rng: np.random.Generator, st_ids: np.ndarray | None = None,
+               p_st: float = 0.0) -> np.ndarray:
+    """k distinct edge ids.  With p_st > 0 each of the k picks comes from the
+    source/sink edges st_ids with probability p_st (a binomial count, capped by
+    how many there are) and from the other edges otherwise: the paper's
+    experiments draw edges out of s and into t more often than the rest."""
+    k = min(int(k), m)
+    if st_ids is None or p_st <= 0.0 or st_ids.shape[0] == 0:
+        return rng.choice(m, size=k, replace=False).astype(np.int64)
+    other = np.setdiff1d(np.arange(m, dtype=np.int64), st_ids, assume_unique=True)
+    k_st = min(int(rng.binomial(k, p_st)), int(st_ids.shape[0]))
+    k_st = max(k_st, k - int(other.shape[0]))
+    a = rng.choice(st_ids, size=k_st, replace=False)
+    b = rng.choice(other, size=k - k_st, replace=False)
+    return rng.permutation(np.concatenate([a, b])).astype(np.int64)
+
+
 def mixed_batch(cur_cap: np.ndarray, k: int, inc_hi: int, rng: np.random.Generator,
-                inc_fraction: float = 0.5, ids: np.ndarray | None = None):
-    """k distinct edges; the first ceil(k*inc_fraction) get cap + U[1, inc_hi],
-    the rest a new capacity U[0, cap]."""
+                inc_fraction: float = 0.5, ids: np.ndarray | None = None,
+                st_ids: np.ndarray | None = None, p_st: float = 0.0):
+    """k distinct edges (pick_edges); the first ceil(k*inc_fraction) get
+    cap + U[1, inc_hi], the rest a new capacity U[0, cap]."""
     m = int(cur_cap.shape[0])
     k = min(int(k), m)
     if ids is None:
-        ids = rng.choice(m, size=k, replace=False).astype(np.int64)
+        ids = pick_edges(m, k, rng, st_ids, p_st)
     else:
         ids = np.asarray(ids, dtype=np.int64)
     n_inc = int(math.ceil(k * inc_fraction))
@@ -213,14 +237,17 @@ def mixed_batch(cur_cap: np.ndarray, k: int, inc_hi: int, rng: np.random.Generat
 
 
 def batch_chain(g: Graph, fraction: float, count: int, inc_hi: int, seed,
-                inc_fraction: float = 0.5, k: int | None = None):
+                inc_fraction: float = 0.5, k: int | None = None, p_st: float = 0.0):
     """Yield `count` successive batches (ids, new_caps); capacities evolve as
     each batch is applied, so batch j is drawn against the capacities that
-    batches 0..j-1 left behind."""
+    batches 0..j-1 left behind.  inc_fraction 1 / 0 / 0.5 gives the paper's
+    incremental, decremental and mixed update families; p_st biases the picks
+    toward edges out of s and into t."""
     cur = g.cap.copy()
     kk = batch_size(g.m, fraction) if k is None else int(k)
+    st = st_edges(g) if p_st > 0.0 else None
     for j in range(count):
-        ids, new = mixed_batch(cur, kk, inc_hi, rng_for(seed, 1, j), inc_fraction)
+        ids, new = mixed_batch(cur, kk, inc_hi, rng_for(seed, 1, j), inc_fraction, st_ids=st, p_st=p_st)
         cur[ids] = new
         yield ids, new
 
