@@ -173,6 +173,53 @@ def test_c3_rmat_static_and_batch(mf):
             check_solved(F, g, cap, oracle="fifo")
 
 
+def _certify_at_any_size(F, g, rp, col, twin):
+    """The validator's local checks in vectorised form (no max-flow route):
+    c_f >= 0, pair sums, every excess equals its residual in-minus-out change,
+    positive excess only on the source side and deficits only on the sink side
+    of the canonical cut, no residual arc from the source side to the sink
+    side, and a cut capacity equal to the value."""
+    cap, cf, e, _, _ = F.export_state()
+    value = F.value()
+    side, cut = F.min_cut()
+    assert cut == value
+    assert (cf >= 0).all()
+    assert np.array_equal(cap.astype(np.int64) + cap[twin], cf.astype(np.int64) + cf[twin])
+    tails = np.repeat(np.arange(g.n, dtype=np.int32), np.diff(rp))
+    booked = np.bincount(tails, weights=(cf.astype(np.int64) - cap).astype(np.float64), minlength=g.n)
+    assert np.array_equal(booked.astype(np.int64), e)
+    inner = np.ones(g.n, dtype=bool)
+    inner[[g.s, g.t]] = False
+    assert (side[(e > 0) & inner] == 1).all() and (side[(e < 0) & inner] == 0).all()
+    assert side[g.s] == 1 and side[g.t] == 0
+    crossing = (side[tails] == 1) & (side[col] == 0)
+    assert not (cf[crossing] > 0).any()
+    assert value == int(e[g.t]) + int(e[inner & (e < 0)].sum())
+    return value
+
+
+def test_c5_full_size_properties(mf):
+    """Config: the served R-MAT scale 22 graph (4,194,304 V, 67,108,864 E) at
+    full size, where the oracle's max-flow routes are too slow for a test:
+    after a static solve and after each of three requests of the served stream
+    (10 to 100k edges, log-uniform), the dynamic value equals a fresh static
+    solve of the same capacities and the exported state passes the
+    validator's local checks (_certify_at_any_size)."""
+    g = W.c5_rmat22()
+    print(f"c5 graph built: n={g.n} m={g.m}", flush=True)
+    with mf.MaxFlow(g) as D, mf.MaxFlow(g) as S:
+        rp, col, twin, _ = D.export_graph()
+        v = D.solve()
+        assert S.solve() == v
+        _certify_at_any_size(D, g, rp, col, twin)
+        for j, (ids, new) in enumerate(W.request_stream(g, 3, W.SEED_BASE + 4)):
+            v = D.update(ids, new)
+            S.set_capacities(ids, new)
+            assert S.solve() == v, j
+            assert _certify_at_any_size(D, g, rp, col, twin) == v
+            print(f"c5 request {j}: {ids.shape[0]} edges, value {v}", flush=True)
+
+
 # ---------------- static comparator path ----------------
 
 def test_set_capacities_then_static_equals_dynamic(mf):
