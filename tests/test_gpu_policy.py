@@ -231,20 +231,34 @@ def _collect_paired(mf, g, count, seed):
     return np.array(X, np.float32), np.array(A, np.int32), np.array(Y, np.float32)
 
 
-def _chain_time(mf, g, count, seed, policy, acts=None):
+def _paired_eval(mf, g, count, seed, policy, acts):
+    """Every call of a held-out chain is replayed from one exported state
+    under the fixed rule and under the learned schedule (the order alternates
+    from call to call); both must give the same value.  Returns the loop time
+    of the chain under each."""
+    tf = tl = 0.0
     with mf.MaxFlow(g) as F:
-        if policy is not None:
-            F.set_policy(policy, mf.MF_POLICY_LEARNED | mf.MF_POLICY_PER_CALL, margin=0.05)
         F.solve()
-        tot = 0.0
-        for ids, new in _chain(g, count, seed):
-            F.update(ids, new)
-            tot += F.stats()["loop_kernel_ms"]
-            if acts is not None and policy is not None:
-                tr = F.policy_trace()
-                if tr.shape[0]:
-                    acts.append(int(tr[0, 16]))
-        return tot, F.value()
+        for j, (ids, new) in enumerate(_chain(g, count, seed)):
+            cap, cf, e, _, ecap = F.export_state()
+            vals = {}
+            for which in ((0, 1) if j % 2 == 0 else (1, 0)):
+                F.import_state(cap, cf, e, ecap)
+                if which == 0:
+                    F.set_policy(None, mf.MF_POLICY_FIXED)
+                else:
+                    F.set_policy(policy, mf.MF_POLICY_LEARNED | mf.MF_POLICY_PER_CALL, margin=0.05)
+                vals[which] = F.update(ids, new)
+                ms = F.stats()["loop_kernel_ms"]
+                if which == 0:
+                    tf += ms
+                else:
+                    tl += ms
+                    tr = F.policy_trace()
+                    if tr.shape[0]:
+                        acts.append(int(tr[0, 16]))
+            assert vals[0] == vals[1]
+    return tf, tl
 
 
 def test_learned_schedule_beats_the_fixed_rule_on_held_out_graphs(mf):
@@ -256,9 +270,9 @@ def test_learned_schedule_beats_the_fixed_rule_on_held_out_graphs(mf):
     ratio of its loop time to the fixed rule's.  The best action differs by
     family and batch size (a shorter relabel budget on grids, longer phases
     on R-MAT at large batches), which one rule cannot serve.  The learned
-    per-call schedule must need less loop time than the fixed rule in total
-    (medians of five alternating repetitions per graph), with identical
-    values."""
+    per-call schedule must need less loop time than the fixed rule in total,
+    with every call of the held-out chains replayed from the same state under
+    both (medians of three repetitions per graph) and identical values."""
     train = [W.rmat(16, 16, 900 + i) for i in range(3)] + [W.rmat(17, 16, 903 + i) for i in range(2)]
     train += [W.seg_grid(128, seed=40), W.seg_grid(160, seed=41), W.seg_grid(160, seed=42),
               W.seg_grid(192, seed=43), W.seg_grid(208, seed=44), W.seg_grid(224, seed=45)]
@@ -275,12 +289,10 @@ def test_learned_schedule_beats_the_fixed_rule_on_held_out_graphs(mf):
         evals = [W.rmat(17, 16, 990), W.rmat(18, 16, 991), W.seg_grid(192, seed=70), W.seg_grid(224, seed=71)]
         for gi, g in enumerate(evals):
             tf, tl, acts = [], [], []
-            for rep in range(5):
-                t, vf = _chain_time(mf, g, 12, 7 + gi, None)
-                tf.append(t)
-                t, vl = _chain_time(mf, g, 12, 7 + gi, P, acts)
-                tl.append(t)
-                assert vl == vf
+            for rep in range(3):
+                a, b = _paired_eval(mf, g, 12, 7 + gi, P, acts)
+                tf.append(a)
+                tl.append(b)
             fixed_total += float(np.median(tf))
             learned_total += float(np.median(tl))
             print(f"  graph {gi}: fixed {np.median(tf):.1f} ms, learned {np.median(tl):.1f} ms, "
