@@ -261,8 +261,9 @@ def run_serving(args):
           file=sys.stderr, flush=True)
     closed = []
     for j in range(nc):
-        r = S.wait(S.submit(gid, *reqs[j]))
-        closed.append(r)
+        rid = S.submit(gid, *reqs[j])
+        closed.append(S.wait(rid))
+        S.release(rid)
     service = float(np.mean([r["done_ms"] - r["start_ms"] for r in closed]))
     print(f"[bench] closed loop: mean service {service:.1f} ms", file=sys.stderr, flush=True)
     phases = {}
@@ -282,6 +283,8 @@ def run_serving(args):
             rids.append((S.submit(gid, *reqs[nxt + j]), int(reqs[nxt + j][0].shape[0])))
         res = [S.wait(r) for r, _ in rids]
         span = time.perf_counter() - start
+        for r, _ in rids:
+            S.release(r)
         nxt += no
         lat = np.array([r["done_ms"] - r["submit_ms"] for r in res])
         edges = sum(k for _, k in rids)

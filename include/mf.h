@@ -501,10 +501,15 @@ MF_API int mf_server_remove_graph(mf_server_t *s, int32_t graph_id);
  * graph's per-edge limit, or a repeated id. */
 MF_API int mf_server_submit(mf_server_t *s, int32_t graph_id, const int64_t *edge_ids, const int32_t *new_caps,
                             int64_t k, int64_t *request_id);
-/* MF_OK with *out filled once the request is committed; MF_EPENDING before. */
+/* MF_OK with *out filled once the request is committed; MF_EPENDING before.
+ * A committed result stays readable (poll, wait) until mf_server_release. */
 MF_API int mf_server_poll(mf_server_t *s, int64_t request_id, mf_result_t *out);
 /* Block until the request is committed. */
 MF_API int mf_server_wait(mf_server_t *s, int64_t request_id, mf_result_t *out);
+/* Forget a committed request's result, after which its id is unknown; a
+ * long-running caller releases what it has read, or the results it keeps
+ * grow with every request.  MF_EPENDING if not committed yet. */
+MF_API int mf_server_release(mf_server_t *s, int64_t request_id);
 /* Block until every submitted request is committed. */
 MF_API int mf_server_drain(mf_server_t *s);
 /* Version and flow value of the graph's last commit. */

@@ -417,6 +417,14 @@ MF_API int mf_server_wait(mf_server_t *s, int64_t request_id, mf_result_t *out) 
     return MF_OK;
 }
 
+MF_API int mf_server_release(mf_server_t *s, int64_t request_id) {
+    if (!s) return sfail(MF_EINVAL, "null server");
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->done.erase(request_id)) return MF_OK;
+    if (s->open.count(request_id)) return MF_EPENDING;
+    return sfail(MF_EINVAL, "unknown request");
+}
+
 MF_API int mf_server_drain(mf_server_t *s) {
     if (!s) return sfail(MF_EINVAL, "null server");
     std::unique_lock<std::mutex> lk(s->mu);

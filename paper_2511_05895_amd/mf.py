@@ -148,6 +148,7 @@ _SIGS = {
     "mf_server_submit": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int64,
                                    C.POINTER(C.c_int64)]),
     "mf_server_poll": (C.c_int, [C.c_void_p, C.c_int64, C.POINTER(mf_result_t)]),
+    "mf_server_release": (C.c_int, [C.c_void_p, C.c_int64]),
     "mf_server_wait": (C.c_int, [C.c_void_p, C.c_int64, C.POINTER(mf_result_t)]),
     "mf_server_drain": (C.c_int, [C.c_void_p]),
     "mf_server_graph_info": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
@@ -764,6 +765,12 @@ def mf_server_poll(s, request_id: int):
     return None if rc == MF_EPENDING else r.as_dict()
 
 
+def mf_server_release(s, request_id: int) -> bool:
+    """True when released, False while the request is still pending."""
+    rc = _scheck(lib().mf_server_release(s, int(request_id)))
+    return rc == MF_OK
+
+
 def mf_server_wait(s, request_id: int) -> dict:
     r = mf_result_t()
     _scheck(lib().mf_server_wait(s, int(request_id), C.byref(r)))
@@ -835,6 +842,9 @@ class Server:
 
     def wait(self, request_id: int) -> dict:
         return mf_server_wait(self.s, request_id)
+
+    def release(self, request_id: int) -> bool:
+        return mf_server_release(self.s, request_id)
 
     def drain(self):
         mf_server_drain(self.s)

@@ -148,3 +148,9 @@ def test_submit_errors(mf, tenants):
         r = S.wait(rid)
         assert r["version"] == 1 and r["value"] == prefix[1]
         assert S.poll(rid)["value"] == prefix[1]
+        # a released result is gone; releasing it again or polling it is an error
+        assert S.release(rid)
+        for call in (S.poll, S.release):
+            with pytest.raises(mf.MfError) as ei:
+                call(rid)
+            assert ei.value.code == mf.MF_EINVAL

@@ -58,5 +58,6 @@ def test_calls_reject_null_server(mf):
     r = mf.mf_result_t()
     assert mf.lib().mf_server_poll(None, 1, C.byref(r)) == mf.MF_EINVAL
     assert mf.lib().mf_server_drain(None) == mf.MF_EINVAL
+    assert mf.lib().mf_server_release(None, 1) == mf.MF_EINVAL
     rid = C.c_int64()
     assert mf.lib().mf_server_submit(None, 0, None, None, 0, C.byref(rid)) == mf.MF_EINVAL
