@@ -89,10 +89,13 @@ typedef struct {
                                downhill to a root within L rounds);
                                0 = 3, < 0 = no such rule                     */
     int32_t solo_items;     /* a BFS level whose frontier holds at most this
-                               many items (arc ranges of up to 256 arcs) is
-                               expanded by one workgroup alone, with
-                               workgroup barriers between its levels, while
-                               the others wait; 0 = 128, < 0 = never          */
+                               many items (arc ranges of up to 256 arcs), and
+                               a push/relabel round whose list holds at most
+                               this many vertices (none of more than 4096
+                               arcs), is run by one workgroup alone, with
+                               workgroup barriers between its levels or
+                               rounds, while the others wait; 0 = 128,
+                               < 0 = never                                   */
     int32_t reserved[1];    /* must be zero                                   */
 } mf_opts_t;
 

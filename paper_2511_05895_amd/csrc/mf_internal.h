@@ -116,6 +116,9 @@ struct Ctrl {
     int64_t deficit;    // sum of e(v) < 0 over v not in {s, t} at termination
     int64_t e_t;        // e(t) at termination
     int64_t cut;        // cut capacity (k_min_cut)
+    // state of the rounds a workgroup ran alone, handed to the others
+    int64_t solo_last_deliv;
+    int32_t solo_r, solo_done, solo_reason, solo_last_change;
     int64_t stat[kStCount];
 };
 
@@ -168,8 +171,9 @@ struct LoopParams {
     int32_t policy_action;     // forced: the action of every phase
     float batch_fraction;      // edges of the update batch / m (1 for a static solve)
     int32_t policy_per_call;   // 1: the action of a call's first phase holds for all its phases
-    int32_t solo_items;        // a BFS level with at most this many frontier items runs on one
-                               // workgroup alone (workgroup barriers); 0 = never
+    int32_t solo_items;        // a BFS level with at most this many frontier items, and a round
+                               // whose list holds at most this many vertices (none huge), runs on
+                               // one workgroup alone (workgroup barriers); 0 = never
     int32_t combine;           // 1: a workgroup adds up a round's pushes per target vertex before
                                // touching its excess (graphs with vertices of huge degree)
     int32_t pad4_;

@@ -1286,41 +1286,87 @@ __device__ void solve_loop(const DevGraph &g, const Team &tm, const LoopParams &
         int r = 0, reason = 0;
         int64_t last_deliv = -1;
         int last_change = 0;
-        for (;; ++r) {
-            const int rd = r % 3, wr = (r + 1) % 3, rs = (r + 2) % 3;
-            // the round's control words, read together before any decision
-            const int64_t lh = uniform(ld<SC>(reinterpret_cast<const int64_t *>(&c->lst[rd])));
-            const int nu = uniform(ld<SC>(&c->lst[rd].huge));
-            const int64_t prl = uniform(ld<SC>(&c->phase_relabels));
-            const int64_t dl = uniform(ld<SC>(&c->phase_deliv));
-            const int nl = (int)(uint32_t)lh;
-            const int nh = (int)((uint64_t)lh >> 32);
-            if (nl + nh + nu == 0) break;
-            if (r >= round_cap) {
-                reason = 1;
-                break;
+        for (;;) {
+            // A small round list (at most solo_items vertices, none huge) is
+            // worked by the first workgroup alone, round after round with
+            // workgroup barriers, while the others wait at the next grid
+            // barrier; the stretch hands its round count and stall state over
+            // in Ctrl.  It stops where a list grows, or after a quarter of the
+            // barrier's wait limit.
+            const int rd0 = r % 3;
+            const int64_t lh0 = uniform(ld<SC>(reinterpret_cast<const int64_t *>(&c->lst[rd0])));
+            const int nu0 = uniform(ld<SC>(&c->lst[rd0].huge));
+            const int size0 = (int)(uint32_t)lh0 + (int)((uint64_t)lh0 >> 32) + nu0;
+            const bool alone = !topology && tm.size > 1 && nu0 == 0 && size0 > 0 && size0 <= p.solo_items;
+            bool done = false;
+            if (!alone || tm.rank == 0) {
+                const Team rt = alone ? Team{0, 1} : tm;
+                const uint64_t ts = wall_clock64();
+                for (;;) {
+                    const int rd = r % 3, wr = (r + 1) % 3, rs = (r + 2) % 3;
+                    // the round's control words, read together before any decision
+                    const int64_t lh = uniform(ld<SC>(reinterpret_cast<const int64_t *>(&c->lst[rd])));
+                    const int nu = uniform(ld<SC>(&c->lst[rd].huge));
+                    const int64_t prl = uniform(ld<SC>(&c->phase_relabels));
+                    const int64_t dl = uniform(ld<SC>(&c->phase_deliv));
+                    const int nl = (int)(uint32_t)lh;
+                    const int nh = (int)((uint64_t)lh >> 32);
+                    if (nl + nh + nu == 0) {
+                        done = true;
+                        break;
+                    }
+                    if (r >= round_cap) {
+                        reason = 1;
+                        done = true;
+                        break;
+                    }
+                    if (prl > budget) {
+                        reason = 2;
+                        done = true;
+                        break;
+                    }
+                    // all values read here were written before the last barrier, so
+                    // every workgroup of the team takes the same decision
+                    if (dl != last_deliv) {
+                        last_deliv = dl;
+                        last_change = r;
+                    }
+                    if (stall_lim > 0 && r - last_change >= stall_lim) {
+                        reason = 3;
+                        done = true;
+                        break;
+                    }
+                    if (leader) c->lst[rs] = ListCtr{};
+                    const RoundCtx rc{g.list[wr], g.huge[wr], nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                                      nullptr, &c->lst[wr], rbase + r + 1, rbase, p.use_gap != 0};
+                    if (topology) pr_round_topology<SC>(g, rt, p.kc, rc, tl);
+                    else pr_round<SC>(g, rt, rd, nl, nh, nu, p.kc, rc, p.combine ? comb : nullptr, tl);
+                    ++r;
+                    if (!alone) break;
+                    __syncthreads();
+                    const int rdn = r % 3;
+                    const int64_t lhn = uniform(ld<SC>(reinterpret_cast<const int64_t *>(&c->lst[rdn])));
+                    const int nun = uniform(ld<SC>(&c->lst[rdn].huge));
+                    if (nun > 0 || (int)(uint32_t)lhn + (int)((uint64_t)lhn >> 32) > p.solo_items) break;
+                    if (uniform((int64_t)(wall_clock64() - ts)) > p.barrier_ticks / 4) break;
+                }
+                if (alone && threadIdx.x == 0) {
+                    c->solo_r = r;
+                    c->solo_done = done ? 1 : 0;
+                    c->solo_reason = reason;
+                    c->solo_last_change = last_change;
+                    c->solo_last_deliv = last_deliv;
+                }
             }
-            if (prl > budget) {
-                reason = 2;
-                break;
-            }
-            // all values read here were written before the last barrier, so
-            // every workgroup takes the same decision
-            if (dl != last_deliv) {
-                last_deliv = dl;
-                last_change = r;
-            }
-            if (stall_lim > 0 && r - last_change >= stall_lim) {
-                reason = 3;
-                break;
-            }
-            if (leader) c->lst[rs] = ListCtr{};
-            const RoundCtx rc{g.list[wr], g.huge[wr], nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, &c->lst[wr],
-                              rbase + r + 1,
-                              rbase, p.use_gap != 0};
-            if (topology) pr_round_topology<SC>(g, tm, p.kc, rc, tl);
-            else pr_round<SC>(g, tm, rd, nl, nh, nu, p.kc, rc, p.combine ? comb : nullptr, tl);
+            if (!alone && done) break;  // the phase ends for every workgroup alike
             if (!grid_barrier(c, tm, bar_epoch, p.barrier_ticks)) return;
+            if (alone) {
+                r = uniform(ld<SC>(&c->solo_r));
+                reason = uniform(ld<SC>(&c->solo_reason));
+                last_change = uniform(ld<SC>(&c->solo_last_change));
+                last_deliv = uniform(ld<SC>(&c->solo_last_deliv));
+                if (uniform(ld<SC>(&c->solo_done))) break;
+            }
         }
         // --- RemoveInvalidEdges over the vertices that relabelled ---
         const uint64_t tr = wall_clock64();
