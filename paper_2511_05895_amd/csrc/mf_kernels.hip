@@ -1293,11 +1293,14 @@ __device__ void solve_loop(const DevGraph &g, const Team &tm, const LoopParams &
             // barrier; the stretch hands its round count and stall state over
             // in Ctrl.  It stops where a list grows, or after a quarter of the
             // barrier's wait limit.
-            const int rd0 = r % 3;
-            const int64_t lh0 = uniform(ld<SC>(reinterpret_cast<const int64_t *>(&c->lst[rd0])));
-            const int nu0 = uniform(ld<SC>(&c->lst[rd0].huge));
-            const int size0 = (int)(uint32_t)lh0 + (int)((uint64_t)lh0 >> 32) + nu0;
-            const bool alone = !topology && tm.size > 1 && nu0 == 0 && size0 > 0 && size0 <= p.solo_items;
+            bool alone = false;
+            if (tm.size > 1 && !topology && p.solo_items > 0) {  // a one-workgroup team is always alone
+                const int rd0 = r % 3;
+                const int64_t lh0 = uniform(ld<SC>(reinterpret_cast<const int64_t *>(&c->lst[rd0])));
+                const int nu0 = uniform(ld<SC>(&c->lst[rd0].huge));
+                const int size0 = (int)(uint32_t)lh0 + (int)((uint64_t)lh0 >> 32) + nu0;
+                alone = nu0 == 0 && size0 > 0 && size0 <= p.solo_items;
+            }
             bool done = false;
             if (!alone || tm.rank == 0) {
                 const Team rt = alone ? Team{0, 1} : tm;
