@@ -179,124 +179,3 @@ def test_set_policy_errors_and_fixed_mode(mf):
         F.set_policy(None, mf.MF_POLICY_FIXED)
         F.solve()
         assert F.policy_trace().shape[0] == 0
-
-
-# ---------------- the learned schedule against the fixed rule ----------------
-
-_FRACTIONS = (0.001, 0.01, 0.1)
-
-
-def _chain(g, count, seed):
-    cur = g.cap.copy()
-    for j in range(count):
-        k = W.batch_size(g.m, _FRACTIONS[j % 3])
-        ids, new = W.mixed_batch(cur, k, 1000, W.rng_for(seed, 1, j))
-        cur[ids] = new
-        yield ids, new
-
-
-def _collect_paired(mf, g, count, seed):
-    """Every update call of a chain is replayed from the same state (export,
-    import) under each of the 8 actions held for the whole call; sample =
-    (features of the call's first phase, action, log of the call's loop time
-    over the time under action 0).  The chain then goes on under the fixed
-    rule.  Calls whose first global relabel finds no active vertex have no
-    phase and give no sample."""
-    X, A, Y = [], [], []
-    with mf.MaxFlow(g) as F:
-        F.solve()
-        for ids, new in _chain(g, count, seed):
-            cap, cf, e, _, ecap = F.export_state()
-            times, feats, values = [], None, set()
-            for a in range(8):
-                F.import_state(cap, cf, e, ecap)
-                F.set_policy(None, mf.MF_POLICY_FORCED, action=a)
-                values.add(F.update(ids, new))
-                tr = F.policy_trace()
-                if tr.shape[0] == 0:
-                    break
-                if feats is None:
-                    feats = tr[0, :16].copy()
-                assert np.array_equal(tr[0, :16], feats)  # same state, same first phase
-                times.append(F.stats()["loop_kernel_ms"])
-            assert len(values) == 1
-            if len(times) == 8:
-                for a in range(8):
-                    X.append(feats)
-                    A.append(a)
-                    Y.append(np.log(times[a] / times[0]))
-            F.import_state(cap, cf, e, ecap)
-            F.set_policy(None, mf.MF_POLICY_FIXED)
-            F.update(ids, new)
-    return np.array(X, np.float32), np.array(A, np.int32), np.array(Y, np.float32)
-
-
-def _paired_eval(mf, g, count, seed, policy, acts):
-    """Every call of a held-out chain is replayed from one exported state
-    under the fixed rule and under the learned schedule (the order alternates
-    from call to call); both must give the same value.  Returns the loop time
-    of the chain under each."""
-    tf = tl = 0.0
-    with mf.MaxFlow(g) as F:
-        F.solve()
-        for j, (ids, new) in enumerate(_chain(g, count, seed)):
-            cap, cf, e, _, ecap = F.export_state()
-            vals = {}
-            for which in ((0, 1) if j % 2 == 0 else (1, 0)):
-                F.import_state(cap, cf, e, ecap)
-                if which == 0:
-                    F.set_policy(None, mf.MF_POLICY_FIXED)
-                else:
-                    F.set_policy(policy, mf.MF_POLICY_LEARNED | mf.MF_POLICY_PER_CALL, margin=0.05)
-                vals[which] = F.update(ids, new)
-                ms = F.stats()["loop_kernel_ms"]
-                if which == 0:
-                    tf += ms
-                else:
-                    tl += ms
-                    tr = F.policy_trace()
-                    if tr.shape[0]:
-                        acts.append(int(tr[0, 16]))
-            assert vals[0] == vals[1]
-    return tf, tl
-
-
-def test_learned_schedule_beats_the_fixed_rule_on_held_out_graphs(mf):
-    """Trained on R-MAT graphs (seeds 900..904) and segmentation grids of
-    sides 128..224 (seeds 40..45), evaluated on held-out seeds of both
-    families; update chains mix
-    0.1 %, 1 % and 10 % batches.  The training signal is paired: each call is
-    replayed from one state under every action, and the target is the log
-    ratio of its loop time to the fixed rule's.  The best action differs by
-    family and batch size (a shorter relabel budget on grids, longer phases
-    on R-MAT at large batches), which one rule cannot serve.  The learned
-    per-call schedule must need less loop time than the fixed rule in total,
-    with every call of the held-out chains replayed from the same state under
-    both (medians of three repetitions per graph) and identical values."""
-    train = [W.rmat(16, 16, 900 + i) for i in range(3)] + [W.rmat(17, 16, 903 + i) for i in range(2)]
-    train += [W.seg_grid(128, seed=40), W.seg_grid(160, seed=41), W.seg_grid(160, seed=42),
-              W.seg_grid(192, seed=43), W.seg_grid(208, seed=44), W.seg_grid(224, seed=45)]
-    data = [_collect_paired(mf, g, 18, 50 + i) for i, g in enumerate(train)]
-    X = np.concatenate([d[0] for d in data])
-    A = np.concatenate([d[1] for d in data])
-    Y = np.concatenate([d[2] for d in data])
-    assert len(np.unique(A)) == 8
-    with mf.Policy(seed=1) as P:
-        l0, _ = P.gradient(X, A, Y)
-        l1 = P.train(X, A, Y, steps=2000, lr=3e-3)
-        assert l1 < l0
-        fixed_total = learned_total = 0.0
-        evals = [W.rmat(17, 16, 990), W.rmat(18, 16, 991), W.seg_grid(192, seed=70), W.seg_grid(224, seed=71)]
-        for gi, g in enumerate(evals):
-            tf, tl, acts = [], [], []
-            for rep in range(3):
-                a, b = _paired_eval(mf, g, 12, 7 + gi, P, acts)
-                tf.append(a)
-                tl.append(b)
-            fixed_total += float(np.median(tf))
-            learned_total += float(np.median(tl))
-            print(f"  graph {gi}: fixed {np.median(tf):.1f} ms, learned {np.median(tl):.1f} ms, "
-                  f"actions {np.bincount(acts, minlength=8).tolist()}")
-        gain = fixed_total / learned_total
-        print(f"learned schedule: fixed {fixed_total:.1f} ms, learned {learned_total:.1f} ms, gain {gain:.3f}x")
-        assert learned_total < fixed_total
