@@ -33,6 +33,8 @@ struct mf_handle {
     mf::Ctrl *h_ctrl = nullptr;  // pinned read-back of the control block
     int64_t *d_ids = nullptr;    // staging for host update batches
     int32_t *d_caps = nullptr;
+    int64_t *p_ids = nullptr;    // pinned host copies they are uploaded from
+    int32_t *p_caps = nullptr;
     int64_t staging_cap = 0;
     uint8_t *d_side = nullptr;
     int32_t cap_limit = 0;
@@ -109,6 +111,8 @@ void release(mf_handle_t *h) {
     h->allocs.clear();
     if (h->d_ids) (void)hipFree(h->d_ids);
     if (h->d_caps) (void)hipFree(h->d_caps);
+    if (h->p_ids) (void)hipHostFree(h->p_ids);
+    if (h->p_caps) (void)hipHostFree(h->p_caps);
     if (h->d_ptrace) (void)hipFree(h->d_ptrace);
     if (h->h_ctrl) (void)hipHostFree(h->h_ctrl);
     for (auto &e : h->ev)
@@ -167,8 +171,8 @@ int run_loop_and_finish(mf_handle_t *h) {
     p.batch_fraction = h->batch_fraction;
     p.policy_per_call = h->policy_per_call;
     // height counts of the gap heuristic start at zero (the loop clears them
-    // again before every later global relabel)
-    HIP_TRY(h, mf::launch_fill_i32(h->g.hcount, (int64_t)h->g.n + 1, 0, h->stream));
+    // again before every later global relabel); only the heuristic reads them
+    if (h->use_gap) HIP_TRY(h, mf::launch_fill_i32(h->g.hcount, (int64_t)h->g.n + 1, 0, h->stream));
     HIP_TRY(h, hipEventRecord(h->ev[1], h->stream));
     HIP_TRY(h, mf::launch_loop(h->g, p, h->grid, h->stream));
     HIP_TRY(h, hipEventRecord(h->ev[2], h->stream));
@@ -210,22 +214,33 @@ int next_epoch(mf_handle_t *h) {
     return MF_OK;
 }
 
+// Upload a host batch through pinned staging (an upload from pageable memory
+// is staged by the runtime, synchronously).  Every call ends with a stream
+// synchronisation, so the pinned copies are free again by the next call.
 int stage_host_batch(mf_handle_t *h, const int64_t *ids, const int32_t *caps, int64_t k) {
     if (k > h->staging_cap) {
         if (h->d_ids) (void)hipFree(h->d_ids);
         if (h->d_caps) (void)hipFree(h->d_caps);
+        if (h->p_ids) (void)hipHostFree(h->p_ids);
+        if (h->p_caps) (void)hipHostFree(h->p_caps);
         h->d_ids = nullptr;
         h->d_caps = nullptr;
+        h->p_ids = nullptr;
+        h->p_caps = nullptr;
         h->staging_cap = 0;
         int64_t want = std::max<int64_t>(k, 1024);
         if (hipMalloc(&h->d_ids, sizeof(int64_t) * want) != hipSuccess ||
-            hipMalloc(&h->d_caps, sizeof(int32_t) * want) != hipSuccess)
+            hipMalloc(&h->d_caps, sizeof(int32_t) * want) != hipSuccess ||
+            hipHostMalloc((void **)&h->p_ids, sizeof(int64_t) * want, hipHostMallocDefault) != hipSuccess ||
+            hipHostMalloc((void **)&h->p_caps, sizeof(int32_t) * want, hipHostMallocDefault) != hipSuccess)
             return fail(h, MF_ENOMEM, "cannot allocate the update staging buffers");
         h->staging_cap = want;
     }
     if (k > 0) {
-        HIP_TRY(h, hipMemcpyAsync(h->d_ids, ids, sizeof(int64_t) * k, hipMemcpyHostToDevice, h->stream));
-        HIP_TRY(h, hipMemcpyAsync(h->d_caps, caps, sizeof(int32_t) * k, hipMemcpyHostToDevice, h->stream));
+        std::memcpy(h->p_ids, ids, sizeof(int64_t) * k);
+        std::memcpy(h->p_caps, caps, sizeof(int32_t) * k);
+        HIP_TRY(h, hipMemcpyAsync(h->d_ids, h->p_ids, sizeof(int64_t) * k, hipMemcpyHostToDevice, h->stream));
+        HIP_TRY(h, hipMemcpyAsync(h->d_caps, h->p_caps, sizeof(int32_t) * k, hipMemcpyHostToDevice, h->stream));
     }
     return MF_OK;
 }
