@@ -5,7 +5,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -22,7 +24,17 @@ enum class State { NoFlow, Partial, Solved, NeedsSolve };
 
 thread_local std::string g_create_error;
 
+// Registered when the library is loaded, i.e. after the HIP runtime it links
+// against, so it runs before the runtime's own exit handlers.
+std::atomic<bool> g_exiting{false};
+void mark_exiting() { g_exiting.store(true); }
+struct ExitHook {
+    ExitHook() { std::atexit(mark_exiting); }
+} g_exit_hook;
+
 }  // namespace
+
+bool mf::process_exiting() { return g_exiting.load(); }
 
 struct mf_handle {
     int device = 0;
@@ -104,7 +116,7 @@ hipError_t dev_alloc(mf_handle_t *h, T **p, int64_t count) {
 }
 
 void release(mf_handle_t *h) {
-    if (!h) return;
+    if (!h || mf::process_exiting()) return;
     if (h->device >= 0) (void)hipSetDevice(h->device);
     if (h->stream) (void)hipStreamSynchronize(h->stream);
     for (void *p : h->allocs) (void)hipFree(p);

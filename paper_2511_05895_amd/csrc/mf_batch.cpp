@@ -102,7 +102,7 @@ void drop_graph(mf_batch_t *b) {
 }
 
 void release(mf_batch_t *b) {
-    if (!b) return;
+    if (!b || mf::process_exiting()) return;
     (void)hipSetDevice(b->device);
     if (b->stream) (void)hipStreamSynchronize(b->stream);
     drop_graph(b);

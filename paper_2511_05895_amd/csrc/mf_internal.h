@@ -213,6 +213,12 @@ hipError_t launch_adam(float *theta, const float *grad, float *m, float *v, int 
 // Largest co-resident workgroup count of the loop kernel.
 hipError_t loop_max_coresident(int device, int *blocks);
 
+// True once the process has begun to exit (the C atexit handlers run).  The
+// HIP runtime tears itself down in those handlers, so objects released after
+// that point free only their host memory; the device memory goes with the
+// process.
+bool process_exiting();
+
 }  // namespace mf
 
 struct mf_policy;

@@ -55,6 +55,7 @@ struct mf_policy {
 namespace {
 
 void release(mf_policy_t *p) {
+    if (mf::process_exiting()) return;
     (void)hipSetDevice(p->device);
     if (p->stream) (void)hipStreamSynchronize(p->stream);
     for (void *q : {(void *)p->theta, (void *)p->grad, (void *)p->m, (void *)p->v, (void *)p->loss, (void *)p->X,

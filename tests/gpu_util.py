@@ -30,6 +30,9 @@ def check_solved(F, g, cap_now, value=None, full=True, oracle="dinic"):
     the final heights are the exact global-relabel heights of that state."""
     v = F.value()
     t0 = time.time()
+    big = g.n > 100000
+    if big:
+        log(f"checking n={g.n}: oracle ({oracle})")
     if value is None:
         if oracle == "dinic":
             value, side_o, _ = O.dinic(g, cap_now)
@@ -44,15 +47,19 @@ def check_solved(F, g, cap_now, value=None, full=True, oracle="dinic"):
         assert np.array_equal(side, side_o)
     if not full:
         return v
+    if big:
+        log(f"oracle value {value} ({time.time() - t0:.1f}s); layout")
     pg = check_layout(F, g, cap_now)
     cap, cf, e, h, ecap = F.export_state()
     assert np.array_equal(cap, pg.cap)
     assert np.array_equal(ecap, np.asarray(cap_now, dtype=np.int32))
+    if big:
+        log(f"validator ({time.time() - t0:.1f}s)")
     rc, val, vside, _ = O.validate(pg, cf, e)
     assert rc == 0, f"validator check {rc} failed"
     assert val == value
     assert np.array_equal(vside, side)
     assert np.array_equal(h, O.bfs_heights(pg, cf, e))
-    if g.n > 100000:
+    if big:
         log(f"checked n={g.n} value={v} (oracle+validator {time.time() - t0:.1f}s)")
     return v

@@ -147,6 +147,9 @@ def test_batch_errors(mf, mixed):
 
 
 def test_c4_batch_equals_alone_and_oracle(mf):
+    """All 256 instances of the uneven batch: value and canonical cut equal
+    the oracle's (O2 for every instance, O1 as well for the smallest and
+    largest ones), and the batched values equal single-handle solves."""
     gs = W.c4_instances()
     log(f"C4: {len(gs)} instances, sum n {sum(g.n for g in gs)}, sum m {sum(g.m for g in gs)}")
     with mf.Batch(gs) as B:
@@ -154,14 +157,15 @@ def test_c4_batch_equals_alone_and_oracle(mf):
         log(f"C4 batch solve {B.last_ms():.2f} ms")
         again = B.solve()
         assert np.array_equal(vals, again)
-        order = np.argsort([g.m for g in gs])
-        sample = sorted({int(order[0]), int(order[1]), int(order[len(gs) // 2]), int(order[-1]),
-                         int(order[-2]), int(order[-3])})
-        for i in sample:
-            v, side_o, _ = O.dinic(gs[i], gs[i].cap)
+        for i, g in enumerate(gs):
+            v, side_o = O.fifo_push_relabel(g, g.cap)
             assert vals[i] == v, i
             side, cut = B.min_cut(i)
             assert cut == v and np.array_equal(side, side_o), i
+        log("C4: every instance equals the oracle (value and canonical cut)")
+        order = np.argsort([g.m for g in gs])
+        for i in sorted({int(order[0]), int(order[1]), int(order[-1]), int(order[-2])}):
+            assert vals[i] == O.dinic(gs[i], gs[i].cap)[0], i
     for i, g in enumerate(gs):
         with mf.MaxFlow(g) as F:
             assert F.solve() == vals[i], i

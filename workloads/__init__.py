@@ -10,7 +10,8 @@ Conventions
 * A graph is returned as ``Graph(n, row_ptr, col, cap, s, t)``: ``row_ptr`` is
   int64[n+1], ``col`` int32[m] and ``cap`` int32[m]. Edge ``i`` is the CSR
   position ``i``; its tail is the row that holds it. Within a row, edges are
-  sorted by head (stable, so duplicates keep their draw order).
+  sorted by head (stable, so duplicates keep their draw order; R-MAT rows are
+  sorted by head, then capacity).
 * A batch is ``(edge_ids int64[k], new_caps int32[k])`` of *distinct* edge ids
   with absolute new capacities (a batch is a set of edges with new capacities,
   Sec. 4 of the paper). The first ceil(k/2) entries raise the capacity, the
@@ -136,50 +137,105 @@ def c2_grid_512(seed=SEED_BASE + 1) -> Graph:
 # R-MAT power-law graph
 # --------------------------------------------------------------------------
 
-def rmat(scale: int, edge_factor: int, seed, a=0.57, b=0.19, c=0.19,
-         cap_lo: int = 1, cap_hi: int = 1000, permute: bool = True,
-         chunk: int = 1 << 22) -> Graph:
-    """R-MAT(a,b,c,d) with 2^scale vertices and edge_factor*2^scale edges.
-    Self-loops are redrawn, duplicates kept as separate edges, vertex ids
-    randomly permuted. s / t = highest / second-highest total degree (ties to
-    the lower id). Capacities U[cap_lo, cap_hi]."""
-    n = 1 << scale
-    m = edge_factor * n
-    rng = rng_for(seed, 0)
-
-    def draw(cnt: int):
-        u = np.zeros(cnt, dtype=np.int64)
-        v = np.zeros(cnt, dtype=np.int64)
-        for lvl in range(scale):
-            r = rng.random(cnt)
-            ubit = r >= (a + b)
-            vbit = ((r >= a) & (r < a + b)) | (r >= (a + b + c))
-            u |= ubit.astype(np.int64) << lvl
-            v |= vbit.astype(np.int64) << lvl
+def _rmat_chunk(scale: int, cnt: int, rng: np.random.Generator, t1: int, t2: int, t3: int):
+    """cnt R-MAT edges: at every level one 16-bit draw picks the quadrant
+    (below t1: top-left, t1..t2: top-right, t2..t3: bottom-left, else
+    bottom-right); four levels come from one 64-bit draw.  Self-loops are
+    redrawn from the same generator."""
+    def draw(k):
+        u = np.zeros(k, dtype=np.uint32)
+        v = np.zeros(k, dtype=np.uint32)
+        for base in range(0, scale, 4):
+            raw = rng.bit_generator.random_raw(k)
+            for j in range(min(4, scale - base)):
+                r = ((raw >> np.uint64(16 * j)) & np.uint64(0xFFFF)).astype(np.uint16)
+                ge1, ge2, ge3 = r >= t1, r >= t2, r >= t3
+                u |= ge2.astype(np.uint32) << np.uint32(base + j)
+                v |= (ge1 ^ ge2 ^ ge3).astype(np.uint32) << np.uint32(base + j)
         return u, v
 
-    src = np.empty(m, dtype=np.int64)
-    dst = np.empty(m, dtype=np.int64)
-    for lo in range(0, m, chunk):
-        hi = min(m, lo + chunk)
-        u, v = draw(hi - lo)
+    u, v = draw(cnt)
+    bad = np.flatnonzero(u == v)
+    while bad.size:
+        uu, vv = draw(bad.size)
+        u[bad] = uu
+        v[bad] = vv
+        bad = bad[uu == vv]
+    return u, v
+
+
+def rmat(scale: int, edge_factor: int, seed, a=0.57, b=0.19, c=0.19,
+         cap_lo: int = 1, cap_hi: int = 1000, permute: bool = True,
+         chunk: int = 1 << 21, workers: int = 8) -> Graph:
+    """R-MAT(a,b,c,d) with 2^scale vertices and edge_factor*2^scale edges.
+    The quadrant probabilities are taken in units of 2^-16.  Self-loops are
+    redrawn, duplicates kept as separate edges, vertex ids randomly permuted.
+    s / t = highest / second-highest total degree (ties to the lower id).
+    Capacities U[cap_lo, cap_hi].  Edges are drawn in chunks, each from its
+    own seeded stream (so the graph does not depend on `workers`); rows are
+    sorted by head, then capacity."""
+    import concurrent.futures as cf
+    n = 1 << scale
+    m = edge_factor * n
+    t1 = int(round(a * 65536))
+    t2 = int(round((a + b) * 65536))
+    t3 = int(round((a + b + c) * 65536))
+    bounds = [(lo, min(m, lo + chunk)) for lo in range(0, m, chunk)]
+    src = np.empty(m, dtype=np.uint32)
+    dst = np.empty(m, dtype=np.uint32)
+
+    def fill(i):
+        lo, hi = bounds[i]
+        u, v = _rmat_chunk(scale, hi - lo, rng_for(seed, 0, i), t1, t2, t3)
         src[lo:hi] = u
         dst[lo:hi] = v
-    bad = np.nonzero(src == dst)[0]
-    while bad.size:
-        u, v = draw(bad.size)
-        src[bad] = u
-        dst[bad] = v
-        bad = bad[u == v]
+
+    with cf.ThreadPoolExecutor(max(1, workers)) as ex:
+        list(ex.map(fill, range(len(bounds))))
     if permute:
-        perm = rng.permutation(n).astype(np.int64)
+        perm = rng_for(seed, 1).permutation(n).astype(np.uint32)
         src = perm[src]
         dst = perm[dst]
-    cap = rng.integers(cap_lo, cap_hi + 1, m, dtype=np.int64)
+    cap = rng_for(seed, 2).integers(cap_lo, cap_hi + 1, m, dtype=np.int64)
     deg = np.bincount(src, minlength=n) + np.bincount(dst, minlength=n)
     order = np.lexsort((np.arange(n), -deg))  # highest degree first, ties -> lower id
     s, t = int(order[0]), int(order[1])
-    return edges_to_csr(n, src, dst, cap, s, t)
+    return _csr_by_packed_key(n, src, dst, cap, s, t, workers)
+
+
+def _csr_by_packed_key(n: int, src, dst, cap, s: int, t: int, workers: int = 8) -> Graph:
+    """CSR with rows sorted by head, then capacity, through one sort of
+    packed (tail, head, capacity - min) keys; falls back to edges_to_csr when
+    they do not fit 64 bits."""
+    import concurrent.futures as cf
+    cap = np.asarray(cap, dtype=np.int64)
+    m = int(src.shape[0])
+    c0 = int(cap.min()) if m else 0
+    vb = max(1, (n - 1).bit_length())
+    cb = max(1, (int(cap.max()) - c0).bit_length()) if m else 1
+    if 2 * vb + cb > 63:
+        return edges_to_csr(n, src, dst, cap, s, t)
+    key = (src.astype(np.uint64) << np.uint64(vb + cb)) | (dst.astype(np.uint64) << np.uint64(cb)) | \
+        (cap - c0).astype(np.uint64)
+    # sort in slices of tail ranges, side by side
+    nb = 16
+    shift = max(0, vb - 4)
+    bucket = (np.asarray(src) >> shift).astype(np.uint8)
+    key = key[np.argsort(bucket, kind="stable")]
+    edges = np.zeros(nb + 1, dtype=np.int64)
+    np.cumsum(np.bincount(bucket, minlength=nb), out=edges[1:])
+
+    def sort_slice(i):
+        key[edges[i]:edges[i + 1]].sort()
+
+    with cf.ThreadPoolExecutor(max(1, workers)) as ex:
+        list(ex.map(sort_slice, range(nb)))
+    tails = (key >> np.uint64(vb + cb)).astype(np.int64)
+    heads = ((key >> np.uint64(cb)) & np.uint64((1 << vb) - 1)).astype(np.int32)
+    caps = ((key & np.uint64((1 << cb) - 1)).astype(np.int64) + c0).astype(np.int32)
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(np.bincount(tails, minlength=n), out=row_ptr[1:])
+    return Graph(n, row_ptr, heads, caps, int(s), int(t))
 
 
 def c3_rmat20(seed=SEED_BASE + 2) -> Graph:
