@@ -25,6 +25,7 @@
 #ifndef MF_H
 #define MF_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -41,6 +42,7 @@ extern "C" {
 #define MF_ESTATE 4   /* call not allowed in the handle's current state      */
 #define MF_ETIMEOUT 5 /* iteration limit reached before the loop converged   */
 #define MF_EPENDING 6 /* (server) the request has not been committed yet     */
+#define MF_EBUSY 7    /* (server) the request queue is full; nothing queued  */
 
 /* work distribution of the push/relabel and invalid-edge sweeps */
 #define MF_MODE_DATA 0     /* worklist of active vertices (Sec. 5.3)          */
@@ -97,6 +99,15 @@ typedef struct {
                                rounds, while the others wait; 0 = 128,
                                < 0 = never                                   */
     int32_t reserved[1];    /* must be zero                                   */
+    /* Device memory of the handle (optional, both or neither): dev_alloc
+     * returns `bytes` of device memory on opts.device (aligned to 256 bytes)
+     * or NULL, dev_free releases it; both get alloc_ctx.  A caching allocator
+     * (torch's, say) can supply the handle this way.  NULL: hipMalloc and
+     * hipFree.  dev_free is called from mf_destroy, after the handle's
+     * stream has drained. */
+    void *(*dev_alloc)(size_t bytes, void *ctx);
+    void (*dev_free)(void *ptr, void *ctx);
+    void *alloc_ctx;
 } mf_opts_t;
 
 /* opts.flags: turn the gap heuristic on (Sec. 2.2 names gap relabelling as a
@@ -104,6 +115,23 @@ typedef struct {
  * empties a height makes every vertex above it count as cut off from the sink
  * until the next global relabel. */
 #define MF_FLAG_GAP 1
+/* opts.flags: dynamic updates by Dynamic Push-Pull (Sec. 4.2, Alg. 8) instead
+ * of Dynamic Push Relabel (Alg. 4).  After the capacity changes land (Alg. 5),
+ * the vertices the last global relabel reached form T and the rest S; every
+ * residual arc from S to T is saturated; deficient vertices of S pull flow
+ * (Alg. 6, forward BFS from s and the overflowing vertices of S) while
+ * overflowing vertices of T push (backward BFS from t and the deficient
+ * vertices of T), the two sides side by side in one launch; the remaining
+ * excess and deficits meet in P, the vertices neither BFS reached, where the
+ * dynamic push-relabel loop runs on P alone.  Values, cuts and every other
+ * output are the same as without the flag. */
+#define MF_FLAG_PUSH_PULL 2
+/* opts.flags: after every solving call, check the state on the device: c_f >=
+ * 0, every arc pair's residuals sum to its capacities, every excess equals
+ * its vertex's residual change (sum over its arcs of c_f - c), and, once
+ * solved, no active vertex and no residual arc from the source side to the
+ * sink side.  A failed check returns MF_EDEVICE naming it. */
+#define MF_FLAG_DEBUG_CHECKS 4
 
 /* Counters of the last mf_solve / mf_apply_updates* / mf_resume call. */
 typedef struct {
@@ -207,6 +235,20 @@ MF_API int mf_flow_value(const mf_handle_t *h, int64_t *out);
  * side_out: host uint8[n].  MF_ESTATE unless solved. */
 MF_API int mf_min_cut(mf_handle_t *h, uint8_t *side_out, int64_t *cut_cap_out);
 
+/* A maximum flow of the current capacities, per input edge (Sec. 3.1: the
+ * preflow left by the loop becomes a valid flow once every excess of the
+ * source side returns to s and every deficit of the sink side is filled from
+ * t, along residual paths that stay inside their side; the proof of Sec.
+ * 4.1.1 gives both paths).  Runs both returns on the device, on a copy of the
+ * state (the handle's state, value and cut are unchanged), then splits each
+ * arc pair's flow among the input edges merged into it.
+ * flow_out: host int32[m], 0 <= flow_out[i] <= capacity of edge i; flow is
+ * conserved at every vertex other than s and t, and the net flow out of s is
+ * the flow value.  Among parallel edges the split is in no fixed order.
+ * MF_ESTATE unless solved; MF_ENOMEM when the copy cannot be allocated (about
+ * 20 bytes per arc and 40 per vertex, kept until mf_destroy). */
+MF_API int mf_edge_flow(mf_handle_t *h, int32_t *flow_out);
+
 /* Change the iteration limit of later calls (< 0 unlimited; 0 runs no
  * loop round, leaving the state right after initialisation or repair). */
 MF_API int mf_set_max_iterations(mf_handle_t *h, int64_t limit);
@@ -214,15 +256,15 @@ MF_API int mf_set_max_iterations(mf_handle_t *h, int64_t limit);
 /* Counters and timings of the last solving call. */
 MF_API int mf_get_stats(const mf_handle_t *h, mf_stats_t *out);
 
-/* Number of merged arcs A and the per-edge capacity limit: the largest
- * capacity an edge may take, min(2^30, (2^31-1) / (2k)) for k the largest
- * number of input edges between one vertex pair, so that an arc's residual
- * stays inside int32 even after one batch of deltas lands before the clamp. */
 /* Upper bound of the device bytes one handle of a graph with n vertices and
  * m edges allocates (merged arcs bounded by 2m), staging of update batches
  * excluded; -1 for negative sizes.  Used for admission by the server. */
 MF_API int64_t mf_estimate_device_bytes(int32_t n, int64_t m);
 
+/* Number of merged arcs A and the per-edge capacity limit: the largest
+ * capacity an edge may take, min(2^30, (2^31-1) / (2k)) for k the largest
+ * number of input edges between one vertex pair, so that an arc's residual
+ * stays inside int32 even after one batch of deltas lands before the clamp. */
 MF_API int mf_num_arcs(const mf_handle_t *h, int32_t *A_out);
 MF_API int mf_cap_limit(const mf_handle_t *h, int32_t *limit_out);
 
@@ -241,8 +283,10 @@ MF_API int mf_export_state(mf_handle_t *h, int32_t *cap, int32_t *cf, int64_t *e
 
 /* Restore a residual state exported by mf_export_state from a handle of the
  * same graph (cap, cf: int32[A]; e: int64[n]; ecap: int32[m]; host arrays,
- * read during the call).  Checks residuals and capacities for signs and every
- * arc pair's residuals against its capacities; MF_EINVAL otherwise.  The
+ * read during the call).  Checks residuals and capacities for signs, every
+ * arc pair's residuals against its capacities, every arc capacity against the
+ * sum of its edges' capacities, and every excess against its vertex's
+ * residual change (sum over its arcs of c_f - c); MF_EINVAL otherwise.  The
  * handle is left partial: mf_apply_updates* continue from the restored
  * state, mf_resume finishes it (the value is available after either).  Used
  * to replay one update from one state under different schedules. */
@@ -451,10 +495,14 @@ MF_API int mf_get_policy_trace(mf_handle_t *h, float *out, int32_t max_phases, i
  * number of its requests applied so far (at least the request's own sequence
  * number): the value equals the maximum flow of the graph after its first
  * `version` requests.  Different graphs are committed by different workers at
- * the same time on their own streams.  Admission: a graph is accepted only
- * while the device bytes reserved for all resident graphs
- * (mf_estimate_device_bytes + staging for max_group_edges updates) stay within
- * memory_budget; otherwise MF_ENOMEM and nothing changes.
+ * the same time on their own streams, as long as their solve kernels'
+ * workgroups fit on the device together (a commit waits otherwise); a launch
+ * that stops early (time budget, barrier wait) is finished by mf_resume.
+ * Admission: a graph is accepted only while the device bytes reserved for all
+ * resident graphs (mf_estimate_device_bytes + staging for max_group_edges
+ * updates) stay within memory_budget, otherwise MF_ENOMEM and nothing changes;
+ * a request only while the queued requests' bytes stay within
+ * max_pending_bytes, otherwise MF_EBUSY and nothing is queued.
  * All mf_server_* calls are thread-safe; errors are reported per thread by
  * mf_server_last_error().
  * ------------------------------------------------------------------------ */
@@ -465,11 +513,15 @@ typedef struct {
     int32_t workers;            /* threads committing groups (default 4)      */
     int64_t memory_budget;      /* device bytes for resident graphs; 0 = 90 %
                                    of the free device memory at creation     */
-    int64_t max_group_edges;    /* edges one commit may merge (default 2^20;
-                                   a larger single request is still taken)   */
+    int64_t max_group_edges;    /* edges one commit may merge (default 2^20);
+                                   also the largest request submit accepts    */
     int32_t max_group_requests; /* requests one commit may merge (default 64; 1
                                    = no group commit)                         */
-    int32_t reserved[3];        /* must be zero                               */
+    int32_t reserved0;          /* must be zero                               */
+    int64_t max_pending_bytes;  /* host bytes the queued requests may hold (12
+                                   per edge); beyond it mf_server_submit returns
+                                   MF_EBUSY; 0 = 1 GiB                        */
+    int32_t reserved[2];        /* must be zero                               */
 } mf_server_opts_t;
 
 typedef struct {
@@ -501,7 +553,8 @@ MF_API int mf_server_add_graph(mf_server_t *s, const mf_csr_t *g, const int32_t 
 MF_API int mf_server_remove_graph(mf_server_t *s, int32_t graph_id);
 /* Queue one request; returns at once with *request_id.  MF_EINVAL (nothing
  * queued) for an unknown graph, an id outside [0, m), a capacity outside the
- * graph's per-edge limit, or a repeated id. */
+ * graph's per-edge limit, a repeated id, or more than max_group_edges edges;
+ * MF_EBUSY (nothing queued) when the queue's byte limit is reached. */
 MF_API int mf_server_submit(mf_server_t *s, int32_t graph_id, const int64_t *edge_ids, const int32_t *new_caps,
                             int64_t k, int64_t *request_id);
 /* MF_OK with *out filled once the request is committed; MF_EPENDING before.
@@ -520,6 +573,11 @@ MF_API int mf_server_graph_info(mf_server_t *s, int32_t graph_id, int64_t *versi
 /* Reserved device bytes, the budget and the number of commits so far (any
  * pointer may be NULL). */
 MF_API int mf_server_memory(mf_server_t *s, int64_t *reserved, int64_t *budget, int64_t *commits);
+/* Queue bytes held, workgroup slots in use by commits in flight and the
+ * device's total, and how many commits were finished by mf_resume (any
+ * pointer may be NULL). */
+MF_API int mf_server_load(mf_server_t *s, int64_t *pending_bytes, int32_t *slots_used, int32_t *slots,
+                          int64_t *resumed);
 
 #ifdef __cplusplus
 }

@@ -38,6 +38,11 @@ bool mf::process_exiting() { return g_exiting.load(); }
 
 struct mf_handle {
     int device = 0;
+    // device memory of the handle: the caller's allocator, or hipMalloc / hipFree
+    void *(*alloc_fn)(size_t, void *) = nullptr;
+    void (*free_fn)(void *, void *) = nullptr;
+    void *alloc_ctx = nullptr;
+    int32_t debug_checks = 0;
     hipStream_t own_stream = nullptr;
     hipStream_t stream = nullptr;
     mf::DevGraph g{};
@@ -76,6 +81,23 @@ struct mf_handle {
     float *d_ptrace = nullptr;
     float batch_fraction = 1.f;  // of the current call
     int32_t epoch = 0;
+    int64_t nhuge = 0;          // vertices visited by whole workgroups (huge-list capacity)
+    int32_t push_pull = 0;      // dynamic updates by Dynamic Push-Pull (MF_FLAG_PUSH_PULL)
+    // Second view of the state, allocated on the first push-pull update or
+    // flow extraction: part tags, the reversed view with its own state and
+    // work arrays (rv), the forward copy of the flow extraction (fv: own arcs,
+    // excesses, heights and control block, the handle's work arrays), and the
+    // per-arc / per-edge flow buffers.
+    bool views = false;
+    uint8_t *d_part = nullptr;
+    int64_t *d_work = nullptr;
+    mf::DevGraph rv{};
+    mf::DevGraph fv{};
+    int32_t *d_rem = nullptr;
+    int32_t *d_eflow = nullptr;
+    mf::Ctrl *h_vctrl = nullptr;  // pinned read-back of the two views' control blocks
+    int32_t vseq = 1;             // next round id of rv's marks
+    bool teams_fit = false;       // the two-team kernel's grid fits the device at once
     State state = State::NoFlow;
     int64_t value = 0;
     mf_stats_t stats{};
@@ -104,11 +126,26 @@ int hip_fail(mf_handle_t *h, hipError_t e, const char *what) {
         if (_e != hipSuccess) return hip_fail((h), _e, #expr); \
     } while (0)
 
+// Device memory through the caller's allocator when one was given.
+hipError_t raw_alloc(mf_handle_t *h, void **q, size_t bytes) {
+    if (h->alloc_fn) {
+        *q = h->alloc_fn(bytes, h->alloc_ctx);
+        return *q ? hipSuccess : hipErrorOutOfMemory;
+    }
+    return hipMalloc(q, bytes);
+}
+
+void raw_free(mf_handle_t *h, void *q) {
+    if (!q) return;
+    if (h->free_fn) h->free_fn(q, h->alloc_ctx);
+    else (void)hipFree(q);
+}
+
 template <typename T>
 hipError_t dev_alloc(mf_handle_t *h, T **p, int64_t count) {
     size_t bytes = sizeof(T) * (size_t)std::max<int64_t>(count, 1);
     void *q = nullptr;
-    hipError_t e = hipMalloc(&q, bytes);
+    hipError_t e = raw_alloc(h, &q, bytes);
     if (e != hipSuccess) return e;
     h->allocs.push_back(q);
     *p = static_cast<T *>(q);
@@ -119,14 +156,15 @@ void release(mf_handle_t *h) {
     if (!h || mf::process_exiting()) return;
     if (h->device >= 0) (void)hipSetDevice(h->device);
     if (h->stream) (void)hipStreamSynchronize(h->stream);
-    for (void *p : h->allocs) (void)hipFree(p);
+    for (void *p : h->allocs) raw_free(h, p);
     h->allocs.clear();
-    if (h->d_ids) (void)hipFree(h->d_ids);
-    if (h->d_caps) (void)hipFree(h->d_caps);
+    raw_free(h, h->d_ids);
+    raw_free(h, h->d_caps);
     if (h->p_ids) (void)hipHostFree(h->p_ids);
     if (h->p_caps) (void)hipHostFree(h->p_caps);
-    if (h->d_ptrace) (void)hipFree(h->d_ptrace);
+    raw_free(h, h->d_ptrace);
     if (h->h_ctrl) (void)hipHostFree(h->h_ctrl);
+    if (h->h_vctrl) (void)hipHostFree(h->h_vctrl);
     for (auto &e : h->ev)
         if (e) (void)hipEventDestroy(e);
     if (h->own_stream) (void)hipStreamDestroy(h->own_stream);
@@ -153,13 +191,8 @@ void fill_stats(mf_handle_t *h, bool ran_loop) {
     if (hipEventElapsedTime(&cm, h->ev[0], h->ev[3]) == hipSuccess) s.call_ms = cm;
 }
 
-// Launch the persistent loop, read back, interpret the status.
-int run_loop_and_finish(mf_handle_t *h) {
-    if (h->seq > (1 << 30)) {  // keep round ids unique: restart them with clean stamps
-        HIP_TRY(h, mf::launch_fill_i32(h->g.mark, h->g.n, 0, h->stream));
-        HIP_TRY(h, mf::launch_fill_i32(h->g.rmark, h->g.n, 0, h->stream));
-        h->seq = 1;
-    }
+// Loop parameters of the handle's solving calls (schedule included).
+mf::LoopParams loop_params(const mf_handle_t *h) {
     mf::LoopParams p{};
     p.kc = h->kc;
     p.mode = h->mode;
@@ -182,18 +215,65 @@ int run_loop_and_finish(mf_handle_t *h) {
     p.policy_action = h->policy_action;
     p.batch_fraction = h->batch_fraction;
     p.policy_per_call = h->policy_per_call;
+    return p;
+}
+
+// Round ids stamp mark[] and rmark[]; restart them with clean stamps before
+// they could wrap.
+int fresh_round_ids(mf_handle_t *h, mf::DevGraph &g, int32_t &seq) {
+    if (seq > (1 << 30)) {
+        HIP_TRY(h, mf::launch_fill_i32(g.mark, g.n, 0, h->stream));
+        HIP_TRY(h, mf::launch_fill_i32(g.rmark, g.n, 0, h->stream));
+        seq = 1;
+    }
+    return MF_OK;
+}
+
+// Add the counters of an earlier launch of the same call.
+void add_stats(mf_stats_t &s, const mf_stats_t &x) {
+    s.iterations += x.iterations;
+    s.global_relabels += x.global_relabels;
+    s.bfs_levels += x.bfs_levels;
+    s.bfs_vertices += x.bfs_vertices;
+    s.bfs_arcs += x.bfs_arcs;
+    s.pr_vertex_cycles += x.pr_vertex_cycles;
+    s.pr_arcs += x.pr_arcs;
+    s.pushes += x.pushes;
+    s.relabels += x.relabels;
+    s.rie_arcs += x.rie_arcs;
+    s.rie_saturations += x.rie_saturations;
+    s.updates += x.updates;
+    s.clamps += x.clamps;
+    s.source_pushes += x.source_pushes;
+    s.rounds += x.rounds;
+    s.loop_launches += x.loop_launches;
+    s.bfs_ms += x.bfs_ms;
+    s.pr_ms += x.pr_ms;
+    s.rie_ms += x.rie_ms;
+    s.loop_kernel_ms += x.loop_kernel_ms;
+}
+
+// Launch the persistent loop on g (the handle's graph, or a part-restricted
+// view of it), read back, interpret the status.  prior: counters of earlier
+// launches of the same call, added to the call's statistics.
+int run_loop_and_finish(mf_handle_t *h, const mf::DevGraph *gsel = nullptr, const mf_stats_t *prior = nullptr) {
+    int rc = fresh_round_ids(h, h->g, h->seq);
+    if (rc) return rc;
+    const mf::DevGraph &g = gsel ? *gsel : h->g;
+    mf::LoopParams p = loop_params(h);
     // height counts of the gap heuristic start at zero (the loop clears them
     // again before every later global relabel); only the heuristic reads them
     if (h->use_gap) HIP_TRY(h, mf::launch_fill_i32(h->g.hcount, (int64_t)h->g.n + 1, 0, h->stream));
     HIP_TRY(h, hipEventRecord(h->ev[1], h->stream));
-    HIP_TRY(h, mf::launch_loop(h->g, p, h->grid, h->stream));
+    HIP_TRY(h, mf::launch_loop(g, p, h->grid, h->stream));
     HIP_TRY(h, hipEventRecord(h->ev[2], h->stream));
-    int rc = finish_call(h);
+    rc = finish_call(h);
     if (rc) return rc;
     const mf::Ctrl &c = *h->h_ctrl;
     if (c.err) return MF_EINVAL;  // caller reports the message
     h->seq += c.rounds + 1;
     fill_stats(h, true);
+    if (prior) add_stats(h->stats, *prior);
     if (c.status == mf::kSolved) {
         h->state = State::Solved;
         h->value = c.e_t + c.deficit;
@@ -227,12 +307,14 @@ int next_epoch(mf_handle_t *h) {
 }
 
 // Upload a host batch through pinned staging (an upload from pageable memory
-// is staged by the runtime, synchronously).  Every call ends with a stream
-// synchronisation, so the pinned copies are free again by the next call.
+// is staged by the runtime, synchronously).  A call that failed part-way may
+// have left the previous copies queued, so the stream is drained before the
+// pinned buffers are written or freed (a no-op after a completed call).
 int stage_host_batch(mf_handle_t *h, const int64_t *ids, const int32_t *caps, int64_t k) {
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
     if (k > h->staging_cap) {
-        if (h->d_ids) (void)hipFree(h->d_ids);
-        if (h->d_caps) (void)hipFree(h->d_caps);
+        raw_free(h, h->d_ids);
+        raw_free(h, h->d_caps);
         if (h->p_ids) (void)hipHostFree(h->p_ids);
         if (h->p_caps) (void)hipHostFree(h->p_caps);
         h->d_ids = nullptr;
@@ -241,8 +323,12 @@ int stage_host_batch(mf_handle_t *h, const int64_t *ids, const int32_t *caps, in
         h->p_caps = nullptr;
         h->staging_cap = 0;
         int64_t want = std::max<int64_t>(k, 1024);
-        if (hipMalloc(&h->d_ids, sizeof(int64_t) * want) != hipSuccess ||
-            hipMalloc(&h->d_caps, sizeof(int32_t) * want) != hipSuccess ||
+        void *qi = nullptr, *qc = nullptr;
+        const bool got_i = raw_alloc(h, &qi, sizeof(int64_t) * want) == hipSuccess;
+        h->d_ids = static_cast<int64_t *>(qi);
+        const bool got_c = got_i && raw_alloc(h, &qc, sizeof(int32_t) * want) == hipSuccess;
+        h->d_caps = static_cast<int32_t *>(qc);
+        if (!got_i || !got_c ||
             hipHostMalloc((void **)&h->p_ids, sizeof(int64_t) * want, hipHostMallocDefault) != hipSuccess ||
             hipHostMalloc((void **)&h->p_caps, sizeof(int32_t) * want, hipHostMallocDefault) != hipSuccess)
             return fail(h, MF_ENOMEM, "cannot allocate the update staging buffers");
@@ -255,6 +341,189 @@ int stage_host_batch(mf_handle_t *h, const int64_t *ids, const int32_t *caps, in
         HIP_TRY(h, hipMemcpyAsync(h->d_caps, h->p_caps, sizeof(int32_t) * k, hipMemcpyHostToDevice, h->stream));
     }
     return MF_OK;
+}
+
+// Allocate the second view of the state (see mf_handle::views).
+int ensure_views(mf_handle_t *h) {
+    if (h->views) return MF_OK;
+    const mf::DevGraph &d = h->g;
+    const int64_t n = d.n, A = d.A, m = d.m;
+    mf::DevGraph r = d;
+    mf::DevGraph f = d;
+    hipError_t e;
+#define VALLOC(ptr, count)                                                                 \
+    do {                                                                                   \
+        if ((e = dev_alloc(h, &(ptr), (count))) != hipSuccess)                             \
+            return fail(h, MF_ENOMEM, std::string("hipMalloc " #ptr ": ") + hipGetErrorString(e)); \
+    } while (0)
+    VALLOC(h->d_part, n);
+    VALLOC(h->d_work, 2);
+    VALLOC(r.arc, A);
+    VALLOC(r.e, n);
+    VALLOC(r.h, n);
+    VALLOC(r.q[0], d.qcap);
+    VALLOC(r.q[1], d.qcap);
+    VALLOC(r.list[0], n);
+    VALLOC(r.list[1], n);
+    VALLOC(r.list[2], n);
+    VALLOC(r.huge[0], h->nhuge);
+    VALLOC(r.huge[1], h->nhuge);
+    VALLOC(r.huge[2], h->nhuge);
+    VALLOC(r.mark, n);
+    VALLOC(r.rmark, n);
+    VALLOC(r.relab, n);
+    VALLOC(r.hcount, n + 1);
+    VALLOC(r.ctrl, 1);
+    VALLOC(f.arc, A);
+    VALLOC(f.e, n);
+    VALLOC(f.h, n);
+    VALLOC(f.ctrl, 1);
+    VALLOC(h->d_rem, A);
+    VALLOC(h->d_eflow, m);
+#undef VALLOC
+    r.ptrace = nullptr;
+    f.ptrace = nullptr;
+    if (!h->h_vctrl &&
+        hipHostMalloc((void **)&h->h_vctrl, 2 * sizeof(mf::Ctrl), hipHostMallocDefault) != hipSuccess)
+        return fail(h, MF_ENOMEM, "pinned control blocks of the views");
+    HIP_TRY(h, mf::launch_fill_i32(r.mark, n, 0, h->stream));
+    HIP_TRY(h, mf::launch_fill_i32(r.rmark, n, 0, h->stream));
+    int tmax = 0;
+    HIP_TRY(h, mf::teams_max_coresident(h->device, &tmax));
+    h->teams_fit = h->grid >= 2 && h->grid <= tmax;
+    h->rv = r;
+    h->fv = f;
+    h->vseq = 1;
+    h->views = true;
+    return MF_OK;
+}
+
+// Part tags from the heights of the last global relabel (T: h < |V|), with
+// the arcs of each part in d_work[0] (S) and d_work[1] (T).
+int tag_parts(mf_handle_t *h) {
+    HIP_TRY(h, mf::launch_fill_i32(reinterpret_cast<int32_t *>(h->d_work), 4, 0, h->stream));
+    HIP_TRY(h, mf::launch_part_from_heights(h->g, h->d_part, h->d_work, h->stream));
+    return MF_OK;
+}
+
+// Run two disjoint views side by side: one cooperative launch of two teams,
+// or, with a one-workgroup handle, one after the other.  a works on the S
+// side (its arcs counted in d_work[0]), b on the T side.  Reads both control
+// blocks back into h_vctrl[0] / h_vctrl[1] and advances the round ids.
+int run_two_views(mf_handle_t *h, const mf::DevGraph &a, mf::LoopParams pa, int32_t &seq_a, const mf::DevGraph &b,
+                  mf::LoopParams pb, int32_t &seq_b) {
+    mf::DevGraph ga = a, gb = b;
+    int rc = fresh_round_ids(h, ga, seq_a);
+    if (rc) return rc;
+    rc = fresh_round_ids(h, gb, seq_b);
+    if (rc) return rc;
+    pa.seq_base = seq_a;
+    pb.seq_base = seq_b;
+    HIP_TRY(h, mf::launch_reset_ctrl(ga, h->stream));
+    HIP_TRY(h, mf::launch_reset_ctrl(gb, h->stream));
+    if (pa.use_gap) HIP_TRY(h, mf::launch_fill_i32(ga.hcount, (int64_t)ga.n + 1, 0, h->stream));
+    if (pb.use_gap) HIP_TRY(h, mf::launch_fill_i32(gb.hcount, (int64_t)gb.n + 1, 0, h->stream));
+    if (h->teams_fit) {
+        HIP_TRY(h, mf::launch_teams(ga, pa, gb, pb, h->d_work, h->grid, h->stream));
+    } else {  // one workgroup (or a grid the two-team kernel cannot hold): one side after the other
+        HIP_TRY(h, mf::launch_loop(ga, pa, h->grid, h->stream));
+        HIP_TRY(h, mf::launch_loop(gb, pb, h->grid, h->stream));
+    }
+    HIP_TRY(h, hipMemcpyAsync(&h->h_vctrl[0], ga.ctrl, sizeof(mf::Ctrl), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(h, hipMemcpyAsync(&h->h_vctrl[1], gb.ctrl, sizeof(mf::Ctrl), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    seq_a += h->h_vctrl[0].rounds + 1;
+    seq_b += h->h_vctrl[1].rounds + 1;
+    for (int i = 0; i < 2; ++i) {
+        const int32_t st = h->h_vctrl[i].status;
+        if (st == mf::kSolved) continue;
+        if (st == mf::kDeadline || st == mf::kIterLimit)
+            return fail(h, MF_ETIMEOUT, "a side of the two-sided loop ran out of its time budget");
+        return fail(h, MF_EDEVICE, "a side of the two-sided loop aborted (grid barrier wait ran out)");
+    }
+    return MF_OK;
+}
+
+// Dynamic Push-Pull (Sec. 4.2, Alg. 8) after the capacity changes of the
+// batch landed (Alg. 5): S / T from the last heights; every residual arc from
+// S to T saturated; then pulls into the deficient vertices of S (from s and
+// the overflowing vertices of S, forward BFS of h_-, as pushes in the
+// reversed view) side by side with pushes out of the overflowing vertices of
+// T (to t and the deficient vertices of T, backward BFS of h_+); then the
+// dynamic push-relabel loop on P, the vertices neither BFS reached.
+int push_pull(mf_handle_t *h) {
+    int rc = ensure_views(h);
+    if (rc) return rc;
+    rc = tag_parts(h);
+    if (rc) return rc;
+    HIP_TRY(h, mf::launch_saturate_cut(h->g, h->d_part, h->stream));
+    HIP_TRY(h, mf::launch_view_make(h->g, h->rv.arc, h->rv.e, 1, h->stream));
+    // S side, reversed: roots s (as the view's sink) and the overflowing
+    // vertices of S (negative in the view); t is the view's never-entered end
+    mf::DevGraph gs = h->rv;
+    gs.s = h->g.t;
+    gs.t = h->g.s;
+    gs.part = h->d_part;
+    gs.part_want = mf::kPartS;
+    gs.part_restrict = 0;
+    // T side, as it is: roots t and the deficient vertices of T
+    mf::DevGraph gt = h->g;
+    gt.part = h->d_part;
+    gt.part_want = mf::kPartT;
+    gt.part_restrict = 0;
+    mf::LoopParams p = loop_params(h);
+    p.policy_mode = mf::kPolicyFixed;
+    p.policy_w = nullptr;
+    p.policy_per_call = 0;
+    HIP_TRY(h, hipEventRecord(h->ev[1], h->stream));
+    rc = run_two_views(h, gs, p, h->vseq, gt, p, h->seq);
+    if (rc) return rc;
+    HIP_TRY(h, hipEventRecord(h->ev[2], h->stream));
+    mf_stats_t first{};
+    {
+        mf_stats_t x{};
+        mf::stats_from_ctrl(h->h_vctrl[0], h->tick_ms, &first);
+        mf::stats_from_ctrl(h->h_vctrl[1], h->tick_ms, &x);
+        add_stats(first, x);
+        first.updates = h->h_ctrl->stat[mf::kStUpdates];  // booked by the repair kernels before the loops
+        first.clamps = h->h_ctrl->stat[mf::kStClamps];
+        float ms = 0.f;
+        first.loop_launches = h->teams_fit ? 1 : 2;
+        if (hipEventElapsedTime(&ms, h->ev[1], h->ev[2]) == hipSuccess) first.loop_kernel_ms = ms;
+    }
+    // the S side's vertices and arc pairs back into the handle's state
+    HIP_TRY(h, mf::launch_view_merge(h->g, h->rv.arc, h->rv.e, h->d_part, mf::kPartS, 1, h->stream));
+    // P: reached by neither BFS; the loop on P alone (roots: its deficient
+    // vertices; the BFS enters only P and leaves every other height alone)
+    HIP_TRY(h, mf::launch_part_localized(h->g, h->rv.h, h->d_part, h->stream));
+    mf::DevGraph gp = h->g;
+    gp.part = h->d_part;
+    gp.part_want = mf::kPartP;
+    gp.part_restrict = 1;
+    HIP_TRY(h, mf::launch_reset_ctrl(h->g, h->stream));
+    return run_loop_and_finish(h, &gp, &first);
+}
+
+// The debug check after a solving call that returned rc: the state's
+// invariants, and once solved the cut's.  Returns rc, or MF_EDEVICE naming the
+// first failed check.
+int debug_check(mf_handle_t *h, int rc) {
+    if (!h->debug_checks || (rc != MF_OK && rc != MF_ETIMEOUT)) return rc;
+    const int solved = rc == MF_OK ? 1 : 0;
+    HIP_TRY(h, mf::launch_check_state(h->g, solved, h->stream));
+    int32_t f = 0;
+    HIP_TRY(h, hipMemcpyAsync(&h->h_ctrl->check, &h->g.ctrl->check, sizeof(int32_t), hipMemcpyDeviceToHost,
+                              h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    f = h->h_ctrl->check;
+    if (!f) return rc;
+    static const char *what[] = {"a negative residual", "an arc pair whose residuals do not sum to its capacities",
+                                 "an excess that differs from its vertex's residual change",
+                                 "an active vertex left after the loop",
+                                 "a residual arc from the source side to the sink side"};
+    for (int b = 0; b < 5; ++b)
+        if (f & (1 << b)) return fail(h, MF_EDEVICE, std::string("debug check failed: ") + what[b]);
+    return fail(h, MF_EDEVICE, "debug check failed");
 }
 
 // Dynamic repair and re-solve with batch arrays already on the device.
@@ -270,11 +539,20 @@ int apply_device(mf_handle_t *h, const int64_t *d_ids, const int32_t *d_caps, in
     HIP_TRY(h, mf::launch_validate_updates(h->g, d_ids, d_caps, k, h->epoch, h->cap_limit, h->stream));
     HIP_TRY(h, mf::launch_apply_delta(h->g, d_ids, d_caps, k, h->stream));
     HIP_TRY(h, mf::launch_clamp(h->g, d_ids, k, h->stream));
-    HIP_TRY(h, mf::launch_saturate_source(h->g, h->stream));
     h->batch_fraction = h->g.m > 0 ? (float)((double)k / (double)h->g.m) : 0.f;
-    rc = run_loop_and_finish(h);
+    if (h->push_pull) {
+        // the batch is checked before anything runs on the two sides
+        HIP_TRY(h, hipMemcpyAsync(h->h_ctrl, h->g.ctrl, sizeof(mf::Ctrl), hipMemcpyDeviceToHost, h->stream));
+        HIP_TRY(h, hipStreamSynchronize(h->stream));
+        if (h->h_ctrl->err) return update_error_text(h, h->h_ctrl->err);
+        h->state = State::Partial;
+        rc = push_pull(h);
+    } else {
+        HIP_TRY(h, mf::launch_saturate_source(h->g, h->stream));
+        rc = run_loop_and_finish(h);
+    }
     if (rc == MF_EINVAL) return update_error_text(h, h->h_ctrl->err);
-    return rc;
+    return debug_check(h, rc);
 }
 
 bool opts_valid(const mf_opts_t &o, std::string *why) {
@@ -285,7 +563,8 @@ bool opts_valid(const mf_opts_t &o, std::string *why) {
     if (o.time_budget_ms < 0) { *why = "time_budget_ms must be >= 0"; return false; }
     if (o.max_rounds < 0) { *why = "max_rounds must be >= 0"; return false; }
     if (o.relabel_budget < 0) { *why = "relabel_budget must be >= 0"; return false; }
-    if (o.flags & ~MF_FLAG_GAP) { *why = "unknown flags"; return false; }
+    if (o.flags & ~(MF_FLAG_GAP | MF_FLAG_PUSH_PULL | MF_FLAG_DEBUG_CHECKS)) { *why = "unknown flags"; return false; }
+    if (!o.dev_alloc != !o.dev_free) { *why = "dev_alloc and dev_free go together"; return false; }
     if (o.reserved[0]) { *why = "reserved fields must be zero"; return false; }
     return true;
 }
@@ -340,6 +619,10 @@ MF_API int mf_create(const mf_csr_t *g, const int32_t *cap, int32_t s, int32_t t
     mf_handle_t *h = new (std::nothrow) mf_handle_t();
     if (!h) return fail(nullptr, MF_ENOMEM, "host allocation failed");
     h->device = o.device;
+    h->alloc_fn = o.dev_alloc;
+    h->free_fn = o.dev_free;
+    h->alloc_ctx = o.alloc_ctx;
+    h->debug_checks = (o.flags & MF_FLAG_DEBUG_CHECKS) ? 1 : 0;
     h->cap_limit = (int32_t)lim;
     h->mode = o.mode;
     h->max_iter = o.max_iterations;
@@ -348,6 +631,7 @@ MF_API int mf_create(const mf_csr_t *g, const int32_t *cap, int32_t s, int32_t t
     h->relabel_budget = o.relabel_budget > 0 ? o.relabel_budget : std::max<int64_t>(1024, n / 16);
     h->rounds_per_level = o.rounds_per_level == 0 ? 1 : (o.rounds_per_level < 0 ? 0 : o.rounds_per_level);
     h->use_gap = (o.flags & MF_FLAG_GAP) ? 1 : 0;
+    h->push_pull = (o.flags & MF_FLAG_PUSH_PULL) ? 1 : 0;
     h->stall_rounds = o.stall_rounds == 0 ? 3 : (o.stall_rounds < 0 ? 0 : o.stall_rounds);
     h->solo_items = o.solo_items == 0 ? kSoloItems : (o.solo_items < 0 ? 0 : o.solo_items);
     // one cycle per visit: rounds re-queue a vertex that keeps excess, so
@@ -380,6 +664,7 @@ MF_API int mf_create(const mf_csr_t *g, const int32_t *cap, int32_t s, int32_t t
     // vertices of huge degree draw pushes from many others at once: add them
     // up per workgroup first
     h->combine = nhuge > 0 ? 1 : 0;
+    h->nhuge = nhuge;
 
     mf::DevGraph &d = h->g;
     d.n = n;
@@ -467,6 +752,14 @@ MF_API int mf_create(const mf_csr_t *g, const int32_t *cap, int32_t s, int32_t t
     if (grid > 1 && grid > maxb)
         return bail(MF_EINVAL, "grid_blocks above the co-resident limit " + std::to_string(maxb));
     h->grid = grid;
+    if (h->push_pull) {
+        // the second view up front: push-pull updates then allocate nothing
+        const int rc = ensure_views(h);
+        if (rc) {
+            const std::string why = h->err;
+            return bail(rc, why);
+        }
+    }
     *out = h;
     return MF_OK;
 }
@@ -486,7 +779,7 @@ MF_API int mf_solve(mf_handle_t *h) {
     HIP_TRY(h, mf::launch_saturate_source(h->g, h->stream));
     h->state = State::Partial;
     h->batch_fraction = 1.f;
-    return run_loop_and_finish(h);
+    return debug_check(h, run_loop_and_finish(h));
 }
 
 MF_API int mf_resume(mf_handle_t *h) {
@@ -496,7 +789,7 @@ MF_API int mf_resume(mf_handle_t *h) {
     HIP_TRY(h, hipSetDevice(h->device));
     HIP_TRY(h, hipEventRecord(h->ev[0], h->stream));
     HIP_TRY(h, mf::launch_reset_ctrl(h->g, h->stream));
-    return run_loop_and_finish(h);
+    return debug_check(h, run_loop_and_finish(h));
 }
 
 MF_API int mf_apply_updates(mf_handle_t *h, const int64_t *edge_ids, const int32_t *new_caps, int64_t k) {
@@ -535,6 +828,52 @@ MF_API int mf_set_capacities(mf_handle_t *h, const int64_t *edge_ids, const int3
     if (rc) return rc;
     if (h->h_ctrl->err) return update_error_text(h, h->h_ctrl->err);
     h->state = State::NeedsSolve;
+    return MF_OK;
+}
+
+MF_API int mf_edge_flow(mf_handle_t *h, int32_t *flow_out) {
+    if (!h) return fail(nullptr, MF_EINVAL, "null handle");
+    if (!flow_out && h->g.m > 0) return fail(h, MF_EINVAL, "null flow array");
+    if (h->state != State::Solved) return fail(h, MF_ESTATE, "not solved");
+    HIP_TRY(h, hipSetDevice(h->device));
+    int rc = ensure_views(h);
+    if (rc) return rc;
+    // S / T: the canonical cut of the final global relabel
+    rc = tag_parts(h);
+    if (rc) return rc;
+    HIP_TRY(h, mf::launch_view_make(h->g, h->fv.arc, h->fv.e, 0, h->stream));
+    HIP_TRY(h, mf::launch_view_make(h->g, h->rv.arc, h->rv.e, 1, h->stream));
+    // S side on a copy, s and t exchanged: its overflowing vertices push their
+    // excess back to s (the copy's sink).  T side reversed: its deficient
+    // vertices, overflowing in the view, push toward t, i.e. t sends them
+    // flow.  Both sides run without RemoveInvalidEdges, so no deficit arises.
+    mf::DevGraph gs = h->fv;
+    gs.s = h->g.t;
+    gs.t = h->g.s;
+    gs.part = h->d_part;
+    gs.part_want = mf::kPartS;
+    gs.part_restrict = 0;
+    mf::DevGraph gt = h->rv;
+    gt.part = h->d_part;
+    gt.part_want = mf::kPartT;
+    gt.part_restrict = 0;
+    mf::LoopParams p = loop_params(h);
+    p.no_rie = 1;
+    p.use_gap = 0;
+    p.max_iter = -1;
+    p.relabel_budget = INT64_MAX / 4;
+    p.policy_mode = mf::kPolicyFixed;
+    p.policy_w = nullptr;
+    p.policy_per_call = 0;
+    p.batch_fraction = 0.f;
+    rc = run_two_views(h, gs, p, h->seq, gt, p, h->vseq);
+    if (rc) return rc;
+    // the T side's arcs and excesses into the copy, then the per-edge split
+    HIP_TRY(h, mf::launch_view_merge(h->fv, h->rv.arc, h->rv.e, h->d_part, mf::kPartT, 1, h->stream));
+    HIP_TRY(h, mf::launch_edge_flow(h->g, h->fv.arc, h->d_rem, h->d_eflow, h->stream));
+    if (h->g.m > 0)
+        HIP_TRY(h, hipMemcpyAsync(flow_out, h->d_eflow, sizeof(int32_t) * h->g.m, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
     return MF_OK;
 }
 
@@ -653,19 +992,33 @@ MF_API int mf_import_state(mf_handle_t *h, const int32_t *cap, const int32_t *cf
     HIP_TRY(h, hipStreamSynchronize(h->stream));
     const mf::DevGraph &d = h->g;
     std::vector<int2> arc((size_t)d.A);
-    std::vector<int32_t> twin((size_t)d.A);
+    std::vector<int32_t> twin((size_t)d.A), e2a((size_t)d.m), rp((size_t)d.n + 1);
     if (d.A) {
         HIP_TRY(h, hipMemcpy(arc.data(), d.arc, sizeof(int2) * d.A, hipMemcpyDeviceToHost));
         HIP_TRY(h, hipMemcpy(twin.data(), d.twin, sizeof(int32_t) * d.A, hipMemcpyDeviceToHost));
     }
+    if (d.m) HIP_TRY(h, hipMemcpy(e2a.data(), d.edge2arc, sizeof(int32_t) * d.m, hipMemcpyDeviceToHost));
+    HIP_TRY(h, hipMemcpy(rp.data(), d.row_ptr, sizeof(int32_t) * (d.n + 1), hipMemcpyDeviceToHost));
     for (int64_t a = 0; a < d.A; ++a) {
         if (cap[a] < 0 || cf[a] < 0) return fail(h, MF_EINVAL, "negative capacity or residual");
         const int64_t b = twin[a];
         if ((int64_t)cf[a] + cf[b] != (int64_t)cap[a] + cap[b])
             return fail(h, MF_EINVAL, "residuals of an arc pair do not sum to its capacities");
     }
-    for (int64_t i = 0; i < d.m; ++i)
+    // arc capacities are the sums of their edges' capacities
+    std::vector<int64_t> capsum((size_t)d.A, 0);
+    for (int64_t i = 0; i < d.m; ++i) {
         if (ecap[i] < 0 || ecap[i] > h->cap_limit) return fail(h, MF_EINVAL, "edge capacity out of range");
+        if (e2a[i] >= 0) capsum[e2a[i]] += ecap[i];
+    }
+    for (int64_t a = 0; a < d.A; ++a)
+        if (capsum[a] != cap[a]) return fail(h, MF_EINVAL, "arc capacities disagree with the edge capacities");
+    // every excess is the vertex's residual change: sum over its arcs of c_f - c
+    for (int32_t u = 0; u < d.n; ++u) {
+        int64_t x = 0;
+        for (int32_t a = rp[u]; a < rp[u + 1]; ++a) x += (int64_t)cf[a] - cap[a];
+        if (x != e[u]) return fail(h, MF_EINVAL, "excesses disagree with the residuals");
+    }
     for (int64_t a = 0; a < d.A; ++a) arc[a].y = cf[a];
     if (d.A) {
         HIP_TRY(h, hipMemcpy(d.arc, arc.data(), sizeof(int2) * d.A, hipMemcpyHostToDevice));
@@ -705,7 +1058,7 @@ MF_API int mf_set_policy(mf_handle_t *h, const mf_policy_t *policy, int32_t mode
         HIP_TRY(h, hipSetDevice(h->device));
         HIP_TRY(h, hipStreamSynchronize(h->stream));
         void *q = nullptr;
-        if (hipMalloc(&q, sizeof(float) * mf::kTraceCap * mf::kPolRec) != hipSuccess)
+        if (raw_alloc(h, &q, sizeof(float) * mf::kTraceCap * mf::kPolRec) != hipSuccess)
             return fail(h, MF_ENOMEM, "cannot allocate the policy trace");
         h->d_ptrace = static_cast<float *>(q);
         h->g.ptrace = h->d_ptrace;

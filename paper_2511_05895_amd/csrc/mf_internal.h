@@ -119,6 +119,8 @@ struct Ctrl {
     // state of the rounds a workgroup ran alone, handed to the others
     int64_t solo_last_deliv;
     int32_t solo_r, solo_done, solo_reason, solo_last_change;
+    int32_t check;      // failed invariants of the debug check (bits, see k_check_state)
+    int32_t pad_;
     int64_t stat[kStCount];
 };
 
@@ -148,7 +150,16 @@ struct DevGraph {
     int32_t n_heavy_all;
     float *ptrace;      // kTraceCap x kPolRec policy-trace records, or null
     Ctrl *ctrl;
+    // Optional part tags (null: none).  Only vertices tagged part_want can be
+    // BFS roots; with part_restrict the BFS also enters only such vertices and
+    // the height reset leaves every other vertex's height as it is.
+    const uint8_t *part;
+    int32_t part_want;
+    int32_t part_restrict;
 };
+
+// Part tags of the push-pull update and of the flow extraction.
+enum : uint8_t { kPartS = 0, kPartT = 1, kPartP = 2 };
 
 struct LoopParams {
     int32_t kc;              // KERNELCYCLES: push/relabel operations per vertex visit
@@ -176,7 +187,8 @@ struct LoopParams {
                                // one workgroup alone (workgroup barriers); 0 = never
     int32_t combine;           // 1: a workgroup adds up a round's pushes per target vertex before
                                // touching its excess (graphs with vertices of huge degree)
-    int32_t pad4_;
+    int32_t no_rie;            // 1: no RemoveInvalidEdges (pushes never exceed the excess, so no
+                               // deficit is created; the flow extraction needs that)
 };
 
 // Result of one instance of a batched solve.
@@ -197,6 +209,10 @@ hipError_t launch_apply_delta(const DevGraph &g, const int64_t *ids, const int32
 hipError_t launch_clamp(const DevGraph &g, const int64_t *ids, int64_t k, hipStream_t st);
 hipError_t launch_loop(const DevGraph &g, const LoopParams &p, int grid, hipStream_t st);
 hipError_t launch_min_cut(const DevGraph &g, uint8_t *d_side, hipStream_t st);
+// Invariant check of the state into ctrl->check (cleared first): 1 c_f < 0,
+// 2 pair sum broken, 4 excess != residual change, and when solved 8 active
+// vertex left, 16 residual arc from the source side to the sink side.
+hipError_t launch_check_state(const DevGraph &g, int solved, hipStream_t st);
 // Batched solve: `count` workgroups of `block` threads (256, 512 or 1024);
 // workgroup j solves instance order[j] of graphs[] from scratch with
 // KERNELCYCLES kc[order[j]] and writes res[order[j]].
@@ -212,6 +228,25 @@ hipError_t launch_mlp_forward(const float *theta, const float *X, int N, float *
 hipError_t launch_adam(float *theta, const float *grad, float *m, float *v, int step, float lr, hipStream_t st);
 // Largest co-resident workgroup count of the loop kernel.
 hipError_t loop_max_coresident(int device, int *blocks);
+// Two solve loops side by side in one cooperative launch of `grid` (>= 2)
+// workgroups, split by the arc counts work[0] (view a) and work[1] (view b);
+// the views must touch disjoint vertices and arc pairs.
+hipError_t launch_teams(const DevGraph &ga, const LoopParams &pa, const DevGraph &gb, const LoopParams &pb,
+                        const int64_t *work, int grid, hipStream_t st);
+hipError_t teams_max_coresident(int device, int *blocks);
+// part[v] = T if h(v) < |V| else S; work[0] += arcs of S, work[1] += arcs of T.
+hipError_t launch_part_from_heights(const DevGraph &g, uint8_t *part, int64_t *work, hipStream_t st);
+// part[v] = P where neither g.h nor hv reached v.
+hipError_t launch_part_localized(const DevGraph &g, const int32_t *hv, uint8_t *part, hipStream_t st);
+// Saturate every residual arc from an S vertex to a T vertex.
+hipError_t launch_saturate_cut(const DevGraph &g, const uint8_t *part, hipStream_t st);
+// View of the state (rev: reversed arcs, negated excesses) and its write-back
+// for the arcs and vertices tagged `want`.
+hipError_t launch_view_make(const DevGraph &g, int2 *varc, int64_t *ve, int rev, hipStream_t st);
+hipError_t launch_view_merge(const DevGraph &g, const int2 *varc, const int64_t *ve, const uint8_t *part,
+                             uint8_t want, int rev, hipStream_t st);
+// Per-edge flow (int32[m]) of the valid flow whose residuals are carc[].y.
+hipError_t launch_edge_flow(const DevGraph &g, const int2 *carc, int32_t *rem, int32_t *flow, hipStream_t st);
 
 // True once the process has begun to exit (the C atexit handlers run).  The
 // HIP runtime tears itself down in those handlers, so objects released after

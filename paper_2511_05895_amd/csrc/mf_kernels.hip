@@ -251,7 +251,9 @@ __device__ void flush_tally(Ctrl *c, Tally &t) {
 // ---------------------------------------------------------------------------
 
 // Height reset: t and every deficient vertex other than s are roots (height
-// 0); all others get |V|.  Roots become the level-0 frontier.
+// 0); all others get |V|.  Roots become the level-0 frontier.  With part
+// tags, only vertices of the wanted part can be roots, and with part_restrict
+// the heights of the other vertices are left alone.
 template <int SC>
 __device__ void bfs_roots(const DevGraph &g, const Team &tm, bool counts, bool feats, Tally &tl) {
     const int64_t gtid = tm.tid();
@@ -262,8 +264,11 @@ __device__ void bfs_roots(const DevGraph &g, const Team &tm, bool counts, bool f
         bool root = false;
         int beg = 0, end = 0;
         if (i < g.n) {
-            root = (v == g.t) || (v != g.s && g.e[v] < 0);
-            g.h[v] = root ? 0 : g.n;
+            const bool mine = !g.part || g.part[v] == g.part_want;
+            if (mine || !g.part_restrict) {
+                root = mine && ((v == g.t) || (v != g.s && g.e[v] < 0));
+                g.h[v] = root ? 0 : g.n;
+            }
             if (root) {
                 beg = g.row_ptr[v];
                 end = g.row_ptr[v + 1];
@@ -382,7 +387,7 @@ __device__ void bfs_level(const DevGraph &g, const Team &tm, int L, int cnt, boo
                 const int hv = g.h[v];
                 const int cft = g.arc[tw].y;
                 tl.bfs_a++;
-                if (v != g.s && hv == n && cft > 0) {
+                if (v != g.s && hv == n && cft > 0 && (!g.part_restrict || g.part[v] == g.part_want)) {
                     // the candidate's row bounds and excess load alongside the
                     // compare-and-swap that decides the discovery
                     vbeg = g.row_ptr[v];
@@ -1374,7 +1379,7 @@ __device__ void solve_loop(const DevGraph &g, const Team &tm, const LoopParams &
         // --- RemoveInvalidEdges over the vertices that relabelled ---
         const uint64_t tr = wall_clock64();
         const int nrel = uniform(ld<SC>(&c->nrelab));
-        remove_invalid<SC>(g, tm, g.relab, nrel, p.use_gap != 0, tl);
+        if (!p.no_rie) remove_invalid<SC>(g, tm, g.relab, nrel, p.use_gap != 0, tl);
         if (counts)
             for (int64_t i = tm.tid(); i <= g.n; i += tm.nthreads()) g.hcount[i] = 0;
         {
@@ -1447,6 +1452,152 @@ __global__ void __launch_bounds__(BLOCK) k_loop(DevGraph g, LoopParams p) {
         comb = &s_comb;
     }
     solve_loop<SC>(g, Team{(int)blockIdx.x, (int)gridDim.x}, p, stage, comb);
+}
+
+// Two teams in one cooperative launch: workgroups [0, split) run the solve
+// loop on view a, the others on view b, each view with its own state and
+// control block (its own barrier).  The views must touch disjoint arc pairs
+// and vertices (the S and T sides of a cut with no residual arc from S to
+// T).  split follows the arc counts work[0] (view a) and work[1] (view b),
+// at least one workgroup each.
+template <int BLOCK>
+__global__ void __launch_bounds__(BLOCK)
+    k_teams(DevGraph ga, LoopParams pa, DevGraph gb, LoopParams pb, const int64_t *work) {
+    __shared__ BfsStage s_stage;
+    __shared__ Combine s_comb;
+    if (threadIdx.x < 4) s_stage.cnt[threadIdx.x] = 0;
+    for (int i = threadIdx.x; i < kCombine; i += blockDim.x) {
+        s_comb.key[i] = -1;
+        s_comb.sum[i] = 0;
+    }
+    __syncthreads();
+    const int G = (int)gridDim.x;
+    const int64_t wa = work[0], wb = work[1];
+    int64_t sp = (wa + wb) > 0 ? ((int64_t)G * wa + (wa + wb) / 2) / (wa + wb) : G / 2;
+    const int split = (int)min((int64_t)G - 1, max((int64_t)1, sp));
+    if ((int)blockIdx.x < split)
+        solve_loop<kAgent>(ga, Team{(int)blockIdx.x, split}, pa, &s_stage, pa.combine ? &s_comb : nullptr);
+    else
+        solve_loop<kAgent>(gb, Team{(int)blockIdx.x - split, G - split}, pb, &s_stage,
+                           pb.combine ? &s_comb : nullptr);
+}
+
+// ---------------------------------------------------------------------------
+// Part tags and views of the residual state (Dynamic Push-Pull, Sec. 4.2 /
+// Alg. 8; returning excess to s and filling deficits from t, Sec. 3.1 and the
+// proof of Sec. 4.1.1)
+// ---------------------------------------------------------------------------
+
+// part[v] = T when the last global relabel reached v (h < |V|: v reaches t or
+// a deficient vertex in the residual graph), S otherwise (Alg. 8 first loop).
+// work[0] / work[1] receive the arcs of the S / T vertices (cleared before).
+__global__ void k_part_from_heights(DevGraph g, uint8_t *part, int64_t *work) {
+    int64_t ws = 0, wt = 0;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < g.n;
+         v += (int64_t)gridDim.x * blockDim.x) {
+        const bool tside = g.h[v] < g.n;
+        part[v] = tside ? kPartT : kPartS;
+        const int64_t d = g.row_ptr[v + 1] - g.row_ptr[v];
+        if (tside) wt += d;
+        else ws += d;
+    }
+    ws = wave_sum(ws);
+    wt = wave_sum(wt);
+    if (lane_id() == 0) {
+        if (ws) add<kAgent>(&work[0], ws);
+        if (wt) add<kAgent>(&work[1], wt);
+    }
+}
+
+// After the two teams of a push-pull update: vertices that neither the
+// backward BFS (heights h, from t and the deficient vertices of T) nor the
+// forward BFS (heights hv, from s and the overflowing vertices of S) reached
+// form P (Alg. 8, the localized stage); the others keep their side.
+__global__ void k_part_localized(DevGraph g, const int32_t *hv, uint8_t *part) {
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < g.n;
+         v += (int64_t)gridDim.x * blockDim.x)
+        if (g.h[v] >= g.n && hv[v] >= g.n) part[v] = kPartP;
+}
+
+// Saturate every residual arc from S to T (Alg. 8, "remove S to T edges"),
+// booking the moved flow as excess at the head and deficit at the tail (the
+// paper recomputes every excess afterwards; the change is the same).
+__global__ void k_saturate_cut(DevGraph g, const uint8_t *part) {
+    for (int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; a < g.A;
+         a += (int64_t)gridDim.x * blockDim.x) {
+        const int2 r = g.arc[a];
+        if (r.y <= 0 || part[r.x] != kPartT) continue;
+        const int32_t tw = g.twin[a];
+        const int u = g.arc[tw].x;  // tail of a
+        if (part[u] != kPartS) continue;
+        g.arc[a].y = 0;  // only this thread touches the pair: its twin runs T -> S
+        add<kAgent>(cf_ptr(g.arc, tw), r.y);
+        add<kAgent>(&g.e[u], -(int64_t)r.y);
+        add<kAgent>(&g.e[r.x], (int64_t)r.y);
+    }
+}
+
+// Build a view of the state: rev = 0 copies arcs and excesses; rev = 1 gives
+// arc a = (u, v) the residual of its twin (v, u) and every excess the
+// opposite sign.  In the reversed view, pulling d into u along (v, u)
+// (Alg. 6: c_f(v, u) -= d, c_f(u, v) += d, e(u) += d, e(v) -= d) is pushing d
+// from u to v; the forward BFS of h_- is the backward BFS of the view, and
+// the invalid-edge rule of Alg. 7 is that of Alg. 3 in the view.
+__global__ void k_view_make(DevGraph g, int2 *varc, int64_t *ve, int rev) {
+    const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t a = gtid; a < g.A; a += stride) {
+        const int2 r = g.arc[a];
+        varc[a] = rev ? make_int2(r.x, g.arc[g.twin[a]].y) : r;
+    }
+    for (int64_t v = gtid; v < g.n; v += stride) ve[v] = rev ? -g.e[v] : g.e[v];
+}
+
+// Write back a view's arcs between two vertices tagged `want`, and their
+// excesses (rev: the view is reversed).
+__global__ void k_view_merge(DevGraph g, const int2 *varc, const int64_t *ve, const uint8_t *part,
+                             uint8_t want, int rev) {
+    const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t a = gtid; a < g.A; a += stride) {
+        const int32_t tw = g.twin[a];
+        const int head = g.arc[a].x, tail = g.arc[tw].x;
+        if (part[head] == want && part[tail] == want) g.arc[a].y = rev ? varc[tw].y : varc[a].y;
+    }
+    for (int64_t v = gtid; v < g.n; v += stride)
+        if (part[v] == want) g.e[v] = rev ? -ve[v] : ve[v];
+}
+
+// Per-edge flow from the pair flows of a valid flow.  The flow on arc a is
+// f(a) = cap(a) - c_f(a) where positive; it is shared out among the input
+// edges merged into a, each taking min(its capacity, what is left), so that
+// 0 <= flow <= capacity for every edge and the edges of a carry f(a).  rem
+// (int32[A]) holds what is left per arc; edges of one arc draw from it with a
+// compare-and-swap (in no fixed order among duplicates).
+__global__ void k_arc_flow(DevGraph g, const int2 *carc, int32_t *rem) {
+    for (int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; a < g.A;
+         a += (int64_t)gridDim.x * blockDim.x)
+        rem[a] = max(0, g.cap[a] - carc[a].y);
+}
+
+__global__ void k_edge_flow(DevGraph g, int32_t *rem, int32_t *flow) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < g.m;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t a = g.edge2arc[i];
+        const int32_t c = g.ecap[i];
+        int32_t give = 0;
+        if (a >= 0 && c > 0) {
+            int32_t old = ld<kAgent>(&rem[a]);
+            for (;;) {
+                give = min(c, old);
+                if (give == 0) break;
+                if (__hip_atomic_compare_exchange_strong(&rem[a], &old, old - give, __ATOMIC_RELAXED,
+                                                         __ATOMIC_RELAXED, kAgent))
+                    break;
+            }
+        }
+        flow[i] = give;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1609,6 +1760,38 @@ __global__ void k_fill_i32(int32_t *p, int64_t count, int32_t value) {
         p[i] = value;
 }
 
+static int grid_for(int64_t work, int block, int cap = 8192);
+
+// Invariants of a residual state (the debug check after a solving call).
+__global__ void k_check_state(DevGraph g, int solved) {
+    const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    int32_t f = 0;
+    for (int64_t a = gtid; a < g.A; a += stride) {
+        const int2 r = g.arc[a];
+        const int32_t tw = g.twin[a];
+        const int2 q = g.arc[tw];
+        if (r.y < 0) f |= 1;
+        if ((int64_t)r.y + q.y != (int64_t)g.cap[a] + g.cap[tw]) f |= 2;
+        if (solved && r.y > 0 && g.h[q.x] >= g.n && g.h[r.x] < g.n) f |= 16;  // q.x: tail of a
+    }
+    for (int64_t v = gtid; v < g.n; v += stride) {
+        int64_t x = 0;
+        for (int a = g.row_ptr[v]; a < g.row_ptr[v + 1]; ++a) x += (int64_t)g.arc[a].y - g.cap[a];
+        if (x != g.e[v]) f |= 4;
+        if (solved && v != g.s && v != g.t && g.e[v] > 0 && g.h[v] < g.n) f |= 8;
+    }
+    if (f) atomicOr(&g.ctrl->check, f);
+}
+
+hipError_t launch_check_state(const DevGraph &g, int solved, hipStream_t st) {
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, &g.ctrl->check, (int64_t)1, 0);
+    const int64_t work = g.A > g.n ? g.A : g.n;
+    hipLaunchKernelGGL(k_check_state, dim3(grid_for(work, 256, 4096)), dim3(256), 0, st, g, solved);
+    return hipGetLastError();
+}
+
+
 // ---------------------------------------------------------------------------
 // Batched solve: one workgroup per instance
 // ---------------------------------------------------------------------------
@@ -1661,7 +1844,7 @@ __global__ void __launch_bounds__(BLOCK)
 // launch wrappers
 // ---------------------------------------------------------------------------
 
-static int grid_for(int64_t work, int block, int cap = 8192) {
+static int grid_for(int64_t work, int block, int cap) {
     int64_t b = (work + block - 1) / block;
     if (b < 1) b = 1;
     if (b > cap) b = cap;
@@ -1746,6 +1929,62 @@ hipError_t launch_batch(const DevGraph *graphs, const int32_t *order, int count,
     default:
         return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_teams(const DevGraph &ga, const LoopParams &pa, const DevGraph &gb, const LoopParams &pb,
+                        const int64_t *work, int grid, hipStream_t st) {
+    if (grid < 2) return hipErrorInvalidValue;
+    DevGraph a = ga, b = gb;
+    LoopParams x = pa, y = pb;
+    const int64_t *w = work;
+    void *args[] = {&a, &x, &b, &y, &w};
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_teams<kBlock>), dim3(grid), dim3(kBlock),
+                                      args, 0, st);
+}
+
+hipError_t teams_max_coresident(int device, int *blocks) {
+    int per_cu = 0, cus = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &per_cu, reinterpret_cast<const void *>(k_teams<kBlock>), kBlock, 0);
+    if (e != hipSuccess) return e;
+    e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
+    if (e != hipSuccess) return e;
+    *blocks = per_cu * cus;
+    return hipSuccess;
+}
+
+hipError_t launch_part_from_heights(const DevGraph &g, uint8_t *part, int64_t *work, hipStream_t st) {
+    hipLaunchKernelGGL(k_part_from_heights, dim3(grid_for(g.n, 256, 2048)), dim3(256), 0, st, g, part, work);
+    return hipGetLastError();
+}
+
+hipError_t launch_part_localized(const DevGraph &g, const int32_t *hv, uint8_t *part, hipStream_t st) {
+    hipLaunchKernelGGL(k_part_localized, dim3(grid_for(g.n, 256, 2048)), dim3(256), 0, st, g, hv, part);
+    return hipGetLastError();
+}
+
+hipError_t launch_saturate_cut(const DevGraph &g, const uint8_t *part, hipStream_t st) {
+    hipLaunchKernelGGL(k_saturate_cut, dim3(grid_for(g.A, 256)), dim3(256), 0, st, g, part);
+    return hipGetLastError();
+}
+
+hipError_t launch_view_make(const DevGraph &g, int2 *varc, int64_t *ve, int rev, hipStream_t st) {
+    const int64_t work = g.A > g.n ? g.A : g.n;
+    hipLaunchKernelGGL(k_view_make, dim3(grid_for(work, 256)), dim3(256), 0, st, g, varc, ve, rev);
+    return hipGetLastError();
+}
+
+hipError_t launch_view_merge(const DevGraph &g, const int2 *varc, const int64_t *ve, const uint8_t *part,
+                             uint8_t want, int rev, hipStream_t st) {
+    const int64_t work = g.A > g.n ? g.A : g.n;
+    hipLaunchKernelGGL(k_view_merge, dim3(grid_for(work, 256)), dim3(256), 0, st, g, varc, ve, part, want, rev);
+    return hipGetLastError();
+}
+
+hipError_t launch_edge_flow(const DevGraph &g, const int2 *carc, int32_t *rem, int32_t *flow, hipStream_t st) {
+    if (g.A > 0) hipLaunchKernelGGL(k_arc_flow, dim3(grid_for(g.A, 256)), dim3(256), 0, st, g, carc, rem);
+    if (g.m > 0) hipLaunchKernelGGL(k_edge_flow, dim3(grid_for(g.m, 256)), dim3(256), 0, st, g, rem, flow);
     return hipGetLastError();
 }
 

@@ -13,7 +13,15 @@
 //   receives the flow value and the graph's version (requests applied so far)
 //   after that commit.
 // * Several workers drive different graphs at the same time; each graph's
-//   handle has its own stream, so their kernels overlap on the device.
+//   handle has its own stream, so their kernels overlap on the device.  A
+//   graph's persistent solve kernel is a cooperative grid whose workgroups
+//   must all be resident at once; a commit starts only while the grids in
+//   flight leave room for its grid (workgroup slots of the device), so
+//   concurrent tenants never starve one another's grid barriers.
+// * Requests are admitted by memory: the queued requests' bytes stay within
+//   max_pending_bytes (else MF_EBUSY, nothing queued), and a request may not
+//   exceed the edges one commit stages (max_group_edges), so the staging
+//   reserved with the graph always suffices.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -30,6 +38,7 @@
 #include <vector>
 
 #include "../../include/mf.h"
+#include "mf_internal.h"
 
 namespace {
 
@@ -50,6 +59,7 @@ struct Request {
 
 struct GraphSlot {
     mf_handle_t *h = nullptr;
+    int32_t grid = 1;  // workgroups of its solve kernel
     int32_t n = 0;
     int64_t m = 0;
     int32_t cap_limit = 0;
@@ -79,6 +89,10 @@ struct mf_server {
     int64_t reserved = 0;
     int64_t budget = 0;
     int64_t commits = 0;
+    int64_t pending_bytes = 0;  // host bytes held by queued requests
+    int32_t slots = 0;          // workgroups the device holds at once for a solve kernel
+    int32_t slots_used = 0;     // workgroups of the commits in flight
+    int64_t resumed = 0;        // commits finished by mf_resume after an aborted launch
     bool stop = false;
     std::vector<std::thread> workers;
     std::chrono::steady_clock::time_point t0;
@@ -90,12 +104,17 @@ double now_ms(const mf_server_t *s) {
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - s->t0).count();
 }
 
-// The idle graph whose oldest pending request is the oldest overall.
+// Bytes a queued request holds (ids and capacities).
+int64_t request_bytes(int64_t k) { return 12 * k; }
+
+// The idle graph whose oldest pending request is the oldest overall, among
+// those whose solve grid fits the workgroup slots left.
 GraphSlot *choose(mf_server_t *s, int32_t *gid) {
     GraphSlot *best = nullptr;
     for (size_t i = 0; i < s->graphs.size(); ++i) {
         GraphSlot *g = s->graphs[i].get();
         if (!g->alive || g->busy || g->pending.empty()) continue;
+        if (s->slots_used + g->grid > s->slots) continue;
         if (!best || g->pending.front().id < best->pending.front().id) {
             best = g;
             *gid = (int32_t)i;
@@ -125,6 +144,7 @@ void worker_main(mf_server_t *s) {
             g->pending.pop_front();
         }
         g->busy = true;
+        s->slots_used += g->grid;
         const int failed_before = g->failed;
         lk.unlock();
 
@@ -157,6 +177,16 @@ void worker_main(mf_server_t *s) {
                 caps.push_back(flat[(size_t)(-key[j].second)]);
             }
             rc = mf_apply_updates(g->h, ids.data(), caps.data(), (int64_t)ids.size());
+            // a launch that ran out of its time budget or whose barrier wait
+            // ran out leaves a valid partial state: finish it from there
+            for (int tries = 0; tries < 2 && (rc == MF_ETIMEOUT || rc == MF_EDEVICE); ++tries) {
+                const int r2 = mf_resume(g->h);
+                if (r2 == MF_OK) {
+                    std::lock_guard<std::mutex> lk2(s->mu);
+                    s->resumed++;
+                }
+                rc = r2;
+            }
             if (rc == MF_OK) rc = mf_flow_value(g->h, &value);
             if (rc != MF_OK) why = mf_last_error(g->h);
         }
@@ -171,7 +201,9 @@ void worker_main(mf_server_t *s) {
             g->failure = why;
         }
         s->commits++;
+        s->slots_used -= g->grid;
         for (const Request &r : group) {
+            s->pending_bytes -= request_bytes((int64_t)r.ids.size());
             mf_result_t res;
             std::memset(&res, 0, sizeof(res));
             res.status = rc;
@@ -211,6 +243,7 @@ MF_API void mf_server_default_opts(mf_server_opts_t *o) {
     o->workers = 4;
     o->max_group_edges = 1 << 20;
     o->max_group_requests = 64;
+    o->max_pending_bytes = (int64_t)1 << 30;
 }
 
 MF_API const char *mf_server_last_error(void) { return g_server_error.c_str(); }
@@ -226,6 +259,9 @@ MF_API int mf_server_create(const mf_server_opts_t *opts, mf_server_t **out) {
     if (o.memory_budget < 0) return sfail(MF_EINVAL, "memory_budget must be >= 0");
     if (o.max_group_edges < 1) return sfail(MF_EINVAL, "max_group_edges must be >= 1");
     if (o.max_group_requests < 1) return sfail(MF_EINVAL, "max_group_requests must be >= 1");
+    if (o.max_pending_bytes < 0) return sfail(MF_EINVAL, "max_pending_bytes must be >= 0");
+    if (o.max_pending_bytes == 0) o.max_pending_bytes = (int64_t)1 << 30;
+    if (o.reserved0) return sfail(MF_EINVAL, "reserved fields must be zero");
     for (int32_t r : o.reserved)
         if (r) return sfail(MF_EINVAL, "reserved fields must be zero");
     hipError_t e = hipSetDevice(o.device);
@@ -237,10 +273,14 @@ MF_API int mf_server_create(const mf_server_opts_t *opts, mf_server_t **out) {
             return sfail(MF_EDEVICE, std::string("hipMemGetInfo: ") + hipGetErrorString(e));
         budget = (int64_t)(0.9 * (double)fr);
     }
+    int slots = 0;
+    if ((e = mf::loop_max_coresident(o.device, &slots)) != hipSuccess)
+        return sfail(MF_EDEVICE, std::string("occupancy query: ") + hipGetErrorString(e));
     mf_server_t *s = new (std::nothrow) mf_server_t();
     if (!s) return sfail(MF_ENOMEM, "host allocation failed");
     s->opts = o;
     s->budget = budget;
+    s->slots = std::max(1, slots);
     s->t0 = std::chrono::steady_clock::now();
     try {
         for (int i = 0; i < o.workers; ++i) s->workers.emplace_back(worker_main, s);
@@ -303,9 +343,11 @@ MF_API int mf_server_add_graph(mf_server_t *s, const mf_csr_t *g, const int32_t 
     }
     int64_t v = 0;
     int32_t lim = 0;
+    mf_stats_t st{};
     rc = mf_solve(h);
     if (rc == MF_OK) rc = mf_flow_value(h, &v);
     if (rc == MF_OK) rc = mf_cap_limit(h, &lim);
+    if (rc == MF_OK) rc = mf_get_stats(h, &st);
     if (rc != MF_OK) {
         std::string why = mf_last_error(h);
         mf_destroy(h);
@@ -319,6 +361,7 @@ MF_API int mf_server_add_graph(mf_server_t *s, const mf_csr_t *g, const int32_t 
         return sfail(MF_ENOMEM, "host allocation failed");
     }
     slot->h = h;
+    slot->grid = (int32_t)std::max<int64_t>(1, st.grid_blocks);
     slot->n = g->n;
     slot->m = g->m;
     slot->cap_limit = lim;
@@ -365,6 +408,9 @@ MF_API int mf_server_submit(mf_server_t *s, int32_t graph_id, const int64_t *edg
         lim = s->graphs[graph_id]->cap_limit;
     }
     if (k > m) return sfail(MF_EINVAL, "batch size k must be in [0, m]");
+    if (k > s->opts.max_group_edges)
+        return sfail(MF_EINVAL, "request of " + std::to_string(k) + " edges above the server's max_group_edges (" +
+                                    std::to_string(s->opts.max_group_edges) + ")");
     Request r;
     try {
         r.ids.assign(edge_ids, edge_ids + k);
@@ -386,6 +432,11 @@ MF_API int mf_server_submit(mf_server_t *s, int32_t graph_id, const int64_t *edg
     std::lock_guard<std::mutex> lk(s->mu);
     GraphSlot *g = s->graphs[graph_id].get();
     if (!g->alive || g->removing) return sfail(MF_EINVAL, "unknown graph");
+    if (s->pending_bytes + request_bytes(k) > s->opts.max_pending_bytes)
+        return sfail(MF_EBUSY, "admission: queued requests hold " + std::to_string(s->pending_bytes) + " of " +
+                                   std::to_string(s->opts.max_pending_bytes) +
+                                   " bytes; retry once results are taken");
+    s->pending_bytes += request_bytes(k);
     r.id = s->next_request++;
     r.seq = g->next_seq++;
     r.submit_ms = now_ms(s);
@@ -450,6 +501,17 @@ MF_API int mf_server_memory(mf_server_t *s, int64_t *reserved, int64_t *budget, 
     if (reserved) *reserved = s->reserved;
     if (budget) *budget = s->budget;
     if (commits) *commits = s->commits;
+    return MF_OK;
+}
+
+MF_API int mf_server_load(mf_server_t *s, int64_t *pending_bytes, int32_t *slots_used, int32_t *slots,
+                          int64_t *resumed) {
+    if (!s) return sfail(MF_EINVAL, "null server");
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (pending_bytes) *pending_bytes = s->pending_bytes;
+    if (slots_used) *slots_used = s->slots_used;
+    if (slots) *slots = s->slots;
+    if (resumed) *resumed = s->resumed;
     return MF_OK;
 }
 

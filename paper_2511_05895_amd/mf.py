@@ -12,11 +12,13 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmf.so")
 
-MF_OK, MF_EINVAL, MF_ENOMEM, MF_EDEVICE, MF_ESTATE, MF_ETIMEOUT, MF_EPENDING = range(7)
+MF_OK, MF_EINVAL, MF_ENOMEM, MF_EDEVICE, MF_ESTATE, MF_ETIMEOUT, MF_EPENDING, MF_EBUSY = range(8)
 MF_MODE_DATA, MF_MODE_TOPOLOGY = 0, 1
 MF_FLAG_GAP = 1
+MF_FLAG_PUSH_PULL = 2
+MF_FLAG_DEBUG_CHECKS = 4
 _NAMES = {1: "MF_EINVAL", 2: "MF_ENOMEM", 3: "MF_EDEVICE", 4: "MF_ESTATE", 5: "MF_ETIMEOUT",
-          6: "MF_EPENDING"}
+          6: "MF_EPENDING", 7: "MF_EBUSY"}
 
 
 class MfError(RuntimeError):
@@ -29,12 +31,17 @@ class mf_csr_t(C.Structure):
     _fields_ = [("n", C.c_int32), ("m", C.c_int64), ("row_ptr", C.c_void_p), ("col", C.c_void_p)]
 
 
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
 class mf_opts_t(C.Structure):
     _fields_ = [("kernel_cycles", C.c_int32), ("mode", C.c_int32), ("grid_blocks", C.c_int32),
                 ("device", C.c_int32), ("max_iterations", C.c_int64), ("time_budget_ms", C.c_int32),
                 ("max_rounds", C.c_int32), ("relabel_budget", C.c_int32), ("rounds_per_level", C.c_int32),
                 ("flags", C.c_int32), ("stall_rounds", C.c_int32), ("solo_items", C.c_int32),
-                ("reserved", C.c_int32 * 1)]
+                ("reserved", C.c_int32 * 1), ("dev_alloc", ALLOC_FN), ("dev_free", FREE_FN),
+                ("alloc_ctx", C.c_void_p)]
 
 
 class mf_stats_t(C.Structure):
@@ -69,7 +76,7 @@ class mf_batch_opts_t(C.Structure):
 class mf_server_opts_t(C.Structure):
     _fields_ = [("device", C.c_int32), ("workers", C.c_int32), ("memory_budget", C.c_int64),
                 ("max_group_edges", C.c_int64), ("max_group_requests", C.c_int32),
-                ("reserved", C.c_int32 * 3)]
+                ("reserved0", C.c_int32), ("max_pending_bytes", C.c_int64), ("reserved", C.c_int32 * 2)]
 
 
 class mf_result_t(C.Structure):
@@ -94,6 +101,7 @@ _SIGS = {
     "mf_set_capacities": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64]),
     "mf_resume": (C.c_int, [C.c_void_p]),
     "mf_flow_value": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
+    "mf_edge_flow": (C.c_int, [C.c_void_p, C.c_void_p]),
     "mf_min_cut": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_int64)]),
     "mf_set_max_iterations": (C.c_int, [C.c_void_p, C.c_int64]),
     "mf_get_stats": (C.c_int, [C.c_void_p, C.POINTER(mf_stats_t)]),
@@ -154,6 +162,8 @@ _SIGS = {
     "mf_server_graph_info": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "mf_server_memory": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
                                    C.POINTER(C.c_int64)]),
+    "mf_server_load": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                 C.POINTER(C.c_int64)]),
 }
 
 _lib = None
@@ -249,6 +259,12 @@ def mf_flow_value(h) -> int:
     return int(v.value)
 
 
+def mf_edge_flow(h, m: int) -> np.ndarray:
+    flow = np.zeros(max(m, 1), dtype=np.int32)
+    _check(lib().mf_edge_flow(h, _ptr(flow)), h)
+    return flow[:m]
+
+
 def mf_min_cut(h, n: int):
     side = np.zeros(n, dtype=np.uint8)
     cut = C.c_int64()
@@ -324,13 +340,46 @@ def mf_set_stream(h, stream_ptr: int | None):
 
 # ---------------- convenience wrapper ----------------
 
+class TorchAllocator:
+    """Device memory for a handle from torch's caching allocator: each block
+    is a uint8 tensor kept alive until the library frees it."""
+
+    def __init__(self, device=0, fail_after=None):
+        import torch
+        self._torch = torch
+        self.device = torch.device("cuda", device)
+        self.live = {}
+        self.fail_after = fail_after  # refuse allocations after this many (tests)
+        self.calls = 0
+
+    def alloc(self, nbytes: int) -> int:
+        self.calls += 1
+        if self.fail_after is not None and self.calls > self.fail_after:
+            return 0
+        t = self._torch.empty(max(nbytes, 1), dtype=self._torch.uint8, device=self.device)
+        self.live[t.data_ptr()] = t
+        return t.data_ptr()
+
+    def free(self, ptr: int):
+        self.live.pop(ptr, None)
+
+
 class MaxFlow:
     """Owns one handle.  g: object with n, row_ptr, col, cap, s, t."""
 
     def __init__(self, g, kernel_cycles=0, mode=MF_MODE_DATA, grid_blocks=0, max_iterations=-1,
                  device=0, cap=None, time_budget_ms=0, max_rounds=0, relabel_budget=0,
-                 rounds_per_level=0, flags=0, stall_rounds=0, solo_items=0):
+                 rounds_per_level=0, flags=0, stall_rounds=0, solo_items=0, allocator=None):
+        """allocator: optional object with alloc(nbytes) -> device address (0
+        on failure) and free(address); the handle's device memory then comes
+        from it (e.g. TorchAllocator)."""
         o = mf_default_opts()
+        self._alloc_cbs = None
+        if allocator is not None:
+            # the callbacks must outlive the handle: kept on the object
+            self._alloc_cbs = (ALLOC_FN(lambda nbytes, ctx: allocator.alloc(int(nbytes)) or None),
+                               FREE_FN(lambda ptr, ctx: allocator.free(int(ptr))))
+            o.dev_alloc, o.dev_free = self._alloc_cbs
         o.solo_items = solo_items
         o.time_budget_ms = time_budget_ms
         o.max_rounds = max_rounds
@@ -388,6 +437,9 @@ class MaxFlow:
 
     def min_cut(self):
         return mf_min_cut(self.h, self.n)
+
+    def edge_flow(self) -> np.ndarray:
+        return mf_edge_flow(self.h, self.m)
 
     def stats(self) -> dict:
         return mf_get_stats(self.h)
@@ -794,16 +846,25 @@ def mf_server_memory(s):
     return {"reserved": int(r.value), "budget": int(b.value), "commits": int(c.value)}
 
 
+def mf_server_load(s):
+    pb, su, sl, rs = C.c_int64(), C.c_int32(), C.c_int32(), C.c_int64()
+    _scheck(lib().mf_server_load(s, C.byref(pb), C.byref(su), C.byref(sl), C.byref(rs)))
+    return {"pending_bytes": int(pb.value), "slots_used": int(su.value), "slots": int(sl.value),
+            "resumed": int(rs.value)}
+
+
 class Server:
     """Owns one serving runtime."""
 
-    def __init__(self, workers=4, memory_budget=0, max_group_edges=1 << 20, max_group_requests=64, device=0):
+    def __init__(self, workers=4, memory_budget=0, max_group_edges=1 << 20, max_group_requests=64, device=0,
+                 max_pending_bytes=0):
         o = mf_server_default_opts()
         o.device = device
         o.workers = workers
         o.memory_budget = memory_budget
         o.max_group_edges = max_group_edges
         o.max_group_requests = max_group_requests
+        o.max_pending_bytes = max_pending_bytes
         self.s = mf_server_create(o)
 
     def close(self):
@@ -854,6 +915,9 @@ class Server:
 
     def memory(self) -> dict:
         return mf_server_memory(self.s)
+
+    def load(self) -> dict:
+        return mf_server_load(self.s)
 
 
 # Load at import: a missing or broken library is an ImportError, never a fallback.

@@ -54,6 +54,8 @@ def _create(n, rp, col, cap, s, t, opts=None):
     ("mode", "unknown mode"),
     ("reserved", "reserved"),
     ("cap limit", "per-edge limit"),
+    ("flags", "unknown flags"),
+    ("alloc pair", "go together"),
 ])
 def test_create_rejects_bad_arguments(case, expect):
     from paper_2511_05895_amd import mf
@@ -79,6 +81,12 @@ def test_create_rejects_bad_arguments(case, expect):
         opts.reserved[0] = 1
     elif case == "cap limit":
         cap = [5, 1 << 30]
+    elif case == "flags":
+        opts = mf.mf_default_opts()
+        opts.flags = 64
+    elif case == "alloc pair":
+        opts = mf.mf_default_opts()
+        opts.dev_alloc = mf.ALLOC_FN(lambda nbytes, ctx: None)
     rc, h, msg = _create(n, rp, col, cap, s, t, opts)
     assert rc == mf.MF_EINVAL and not h.value
     assert expect in msg

@@ -164,6 +164,29 @@ def test_import_state_replays_an_update(mf):
         with pytest.raises(mf.MfError) as ei:
             F.import_state(cap, bad, e, ecap)
         assert ei.value.code == mf.MF_EINVAL and "sum" in str(ei.value)
+        # arc capacities must be the sums of their edges' capacities
+        a = int(np.flatnonzero((cap > 0) & (cf > 0))[0])
+        badcap, badcf = cap.copy(), cf.copy()
+        badcap[a] -= 1
+        badcf[a] -= 1  # pair sums still hold
+        with pytest.raises(mf.MfError) as ei:
+            F.import_state(badcap, badcf, e, ecap)
+        assert ei.value.code == mf.MF_EINVAL and "edge capacities" in str(ei.value)
+        badecap = ecap.copy()
+        badecap[0] += 1
+        with pytest.raises(mf.MfError) as ei:
+            F.import_state(cap, cf, e, badecap)
+        assert ei.value.code == mf.MF_EINVAL and "edge capacities" in str(ei.value)
+        # excesses must equal the residual change of their vertex
+        bade = e.copy()
+        bade[5] += 1
+        bade[6] -= 1
+        with pytest.raises(mf.MfError) as ei:
+            F.import_state(cap, cf, bade, ecap)
+        assert ei.value.code == mf.MF_EINVAL and "excesses" in str(ei.value)
+        # the rejected imports changed nothing
+        F.import_state(cap, cf, e, ecap)
+        assert F.update(ids, new) == v1
 
 
 def test_set_policy_errors_and_fixed_mode(mf):

@@ -154,3 +154,68 @@ def test_submit_errors(mf, tenants):
             with pytest.raises(mf.MfError) as ei:
                 call(rid)
             assert ei.value.code == mf.MF_EINVAL
+
+
+def test_mix_of_multi_workgroup_tenants(mf):
+    """Two tenants whose solve kernels are cooperative grids of several
+    workgroups (above the one-workgroup size), served alone and together:
+    every commit equals the oracle's prefix value, and the grids in flight
+    never exceed the device's workgroup slots."""
+    graphs = [W.rmat(15, 8, seed=501), W.grid_instance(160, seed=502)]
+    streams, prefixes = [], []
+    for j, g in enumerate(graphs):
+        with mf.MaxFlow(g) as F:
+            F.solve()
+            assert F.stats()["grid_blocks"] > 1
+        reqs = list(W.request_stream(g, 12, 600 + j, k_lo=10, k_hi=5000))
+        cap = g.cap.copy()
+        prefix = [O.dinic(g, cap)[0]]
+        for ids, new in reqs:
+            cap[ids] = new
+            prefix.append(O.dinic(g, cap)[0])
+        streams.append(reqs)
+        prefixes.append(prefix)
+
+    def run(which):
+        res = {}
+        with mf.Server(workers=4) as S:
+            gids = {j: S.add_graph(graphs[j])[0] for j in which}
+            assert S.load()["slots"] >= 16
+
+            def go(j):
+                rids = [S.submit(gids[j], ids, new) for ids, new in streams[j]]
+                res[j] = [S.wait(r) for r in rids]
+
+            th = [threading.Thread(target=go, args=(j,)) for j in which]
+            for t in th:
+                t.start()
+            for t in th:
+                t.join()
+            load = S.load()
+            assert load["slots_used"] == 0 and load["pending_bytes"] == 0
+        return res
+
+    alone = {j: run([j])[j] for j in range(2)}
+    mix = run([0, 1])
+    for j in range(2):
+        check_results(alone[j], prefixes[j], len(streams[j]))
+        check_results(mix[j], prefixes[j], len(streams[j]))
+
+
+def test_request_admission(mf, tenants):
+    g, reqs, prefix = tenants[0]
+    with mf.Server(workers=1, max_pending_bytes=12 * 50, max_group_edges=200) as S:
+        gid, _ = S.add_graph(g)
+        ids = np.arange(100, dtype=np.int64)
+        caps = g.cap[:100].copy()
+        # a request whose own bytes exceed the queue's limit is turned away, untouched
+        with pytest.raises(mf.MfError) as ei:
+            S.submit(gid, ids, caps)
+        assert ei.value.code == mf.MF_EBUSY and "admission" in str(ei.value)
+        # more edges than one commit stages
+        with pytest.raises(mf.MfError) as ei:
+            S.submit(gid, np.arange(300, dtype=np.int64), g.cap[:300].copy())
+        assert ei.value.code == mf.MF_EINVAL and "max_group_edges" in str(ei.value)
+        r = S.wait(S.submit(gid, ids[:40], caps[:40]))
+        assert r["status"] == 0 and r["value"] == prefix[0]
+        assert S.load()["pending_bytes"] == 0

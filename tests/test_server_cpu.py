@@ -14,7 +14,7 @@ def mf():
 def test_default_opts(mf):
     o = mf.mf_server_default_opts()
     assert o.workers == 4 and o.max_group_edges == 1 << 20 and o.max_group_requests == 64
-    assert o.memory_budget == 0
+    assert o.memory_budget == 0 and o.max_pending_bytes == 1 << 30
 
 
 @pytest.mark.parametrize("field,value,expect", [
@@ -23,6 +23,7 @@ def test_default_opts(mf):
     ("memory_budget", -1, "memory_budget"),
     ("max_group_edges", 0, "max_group_edges"),
     ("max_group_requests", 0, "max_group_requests"),
+    ("max_pending_bytes", -1, "max_pending_bytes"),
     ("device", -1, "device"),
 ])
 def test_create_rejects_bad_options(mf, field, value, expect):
@@ -33,9 +34,13 @@ def test_create_rejects_bad_options(mf, field, value, expect):
     assert ei.value.code == mf.MF_EINVAL and expect in str(ei.value)
 
 
-def test_create_rejects_reserved(mf):
+@pytest.mark.parametrize("which", ["reserved0", "reserved"])
+def test_create_rejects_reserved(mf, which):
     o = mf.mf_server_default_opts()
-    o.reserved[2] = 1
+    if which == "reserved0":
+        o.reserved0 = 1
+    else:
+        o.reserved[1] = 1
     with pytest.raises(mf.MfError) as ei:
         mf.mf_server_create(o)
     assert ei.value.code == mf.MF_EINVAL
