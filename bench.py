@@ -60,6 +60,7 @@ CONFIGS = {
                      base="random graph 1,000 V / 8,000 E", frac=0.0125, inc_hi=100),
     "c4": dict(desc="256 uneven instances (grids 32^2..256^2, random graphs 1k..50k V at degree 8), "
                     "batched static solve"),
+    "learned20": dict(desc="learned vs fixed phase schedule on R-MAT scale 20"),
     "c5": dict(desc="R-MAT scale 22 (4,194,304 V / 67,108,864 E) served: requests of 10..100k edges "
                     "(log-uniform), Poisson arrivals"),
 }
@@ -338,6 +339,128 @@ def run_serving(args):
     print(json.dumps(out), flush=True)
 
 
+_SCHED_FRACTIONS = (0.001, 0.01, 0.1)
+
+
+def _sched_chain(g, count, seed):
+    """Update chain of the schedule comparison: mixed batches of 0.1 %, 1 %
+    and 10 % of the edges in turn, each drawn against the capacities the
+    earlier ones left."""
+    import workloads as W
+    cur = g.cap.copy()
+    for j in range(count):
+        k = W.batch_size(g.m, _SCHED_FRACTIONS[j % 3])
+        ids, new = W.mixed_batch(cur, k, 1000, W.rng_for(seed, 1, j))
+        cur[ids] = new
+        yield ids, new
+
+
+def run_learned(args):
+    """Learned phase schedule against the fixed rule on the R-MAT scale-20
+    graph.  Training: every update call of chains on smaller R-MAT graphs
+    (scales 17 and 18, seeds disjoint from the evaluation graph's) is replayed
+    from one exported state under each of the 8 actions; sample = (features
+    of the call's first phase, action, log of its loop time over the time
+    under action 0).  The value network is trained on the device.
+    Evaluation: every call of a chain on the R-MAT scale-20 graph is replayed
+    from one state under the fixed rule and under the learned per-call
+    schedule (the order alternates), values must match, and the loop times
+    are paired per call: median ratio, two-sided sign test, bootstrap 95 %
+    interval of the mean log ratio."""
+    import torch
+    import workloads as W
+    from paper_2511_05895_amd import mf
+    from scipy.stats import binomtest
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    train = [W.rmat(17, 16, 903 + i) for i in range(2)] + [W.rmat(18, 16, 905 + i) for i in range(2)]
+    X, A, Y = [], [], []
+    for gi, g in enumerate(train):
+        with mf.MaxFlow(g) as F:
+            F.solve()
+            for ids, new in _sched_chain(g, args.train_calls, 50 + gi):
+                cap, cf, e, _, ecap = F.export_state()
+                times, feats, values = [], None, set()
+                for a in range(8):
+                    F.import_state(cap, cf, e, ecap)
+                    F.set_policy(None, mf.MF_POLICY_FORCED, action=a)
+                    values.add(F.update(ids, new))
+                    tr = F.policy_trace()
+                    if tr.shape[0] == 0:
+                        break
+                    if feats is None:
+                        feats = tr[0, :16].copy()
+                    times.append(F.stats()["loop_kernel_ms"])
+                if len(values) != 1:
+                    raise SystemExit("FAIL: actions gave different values")
+                if len(times) == 8:
+                    for a in range(8):
+                        X.append(feats)
+                        A.append(a)
+                        Y.append(np.log(times[a] / times[0]))
+                F.import_state(cap, cf, e, ecap)
+                F.set_policy(None, mf.MF_POLICY_FIXED)
+                F.update(ids, new)
+        print(f"[bench] learned: training graph {gi} (n={g.n}) collected, {len(X)} samples",
+              file=sys.stderr, flush=True)
+    X = np.array(X, np.float32)
+    A = np.array(A, np.int32)
+    Y = np.array(Y, np.float32)
+    g = W.c3_rmat20()
+    fixed, learned, acts = [], [], []
+    with mf.Policy(seed=1) as P, mf.MaxFlow(g) as F:
+        loss = P.train(X, A, Y, steps=2000, lr=3e-3)
+        F.solve()
+        for j, (ids, new) in enumerate(_sched_chain(g, args.steps, W.SEED_BASE + 2 + 100)):
+            cap, cf, e, _, ecap = F.export_state()
+            vals, ms = {}, {}
+            for which in ((0, 1) if j % 2 == 0 else (1, 0)):
+                F.import_state(cap, cf, e, ecap)
+                if which == 0:
+                    F.set_policy(None, mf.MF_POLICY_FIXED)
+                else:
+                    F.set_policy(P, mf.MF_POLICY_LEARNED | mf.MF_POLICY_PER_CALL, margin=0.05)
+                vals[which] = F.update(ids, new)
+                ms[which] = F.stats()["loop_kernel_ms"]
+                if which == 1:
+                    tr = F.policy_trace()
+                    acts.append(int(tr[0, 16]) if tr.shape[0] else 0)
+            if vals[0] != vals[1]:
+                raise SystemExit(f"FAIL: learned value {vals[1]} != fixed value {vals[0]} at call {j}")
+            fixed.append(ms[0])
+            learned.append(ms[1])
+            print(f"[bench] learned: call {j} ({ids.shape[0]} edges): fixed {ms[0]:.2f} ms, "
+                  f"learned {ms[1]:.2f} ms, action {acts[-1]}", file=sys.stderr, flush=True)
+    fixed = np.array(fixed)
+    learned = np.array(learned)
+    lr_ = np.log(learned / fixed)
+    rng = np.random.default_rng(0)
+    boot = [float(np.mean(rng.choice(lr_, lr_.size))) for _ in range(2000)]
+    wins = int((learned < fixed).sum())
+    decided = int((learned != fixed).sum())
+    out = {
+        "metric": "learned vs fixed phase schedule: loop time per update call (paired), exact flow",
+        "value": float(fixed.sum() / learned.sum()),
+        "unit": "x less loop time than the fixed rule (total over the chain)",
+        "n_gpus": 1, "steps": int(fixed.size), "warmup": 0,
+        "ms_per_step": float(learned.mean()),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "int32 capacities / int64 excess; fp32 value network", "data": "synthetic (seeded generator)",
+        "config": {"workload": "R-MAT scale 20 (avg degree 16), mixed 0.1/1/10 % batches; trained on R-MAT "
+                               "scales 17/18 (other seeds)", "n": g.n, "m": g.m,
+                   "train_samples": int(X.shape[0]), "train_loss": loss},
+        "fixed_ms": {"mean": float(fixed.mean()), "p50": float(np.median(fixed))},
+        "learned_ms": {"mean": float(learned.mean()), "p50": float(np.median(learned))},
+        "per_call_ratio": {"median": float(np.exp(np.median(lr_))),
+                           "mean_log_ci95": [float(np.percentile(boot, 2.5)), float(np.percentile(boot, 97.5))]},
+        "sign_test": {"learned_faster": wins, "calls": decided,
+                      "p_two_sided": float(binomtest(wins, decided, 0.5).pvalue) if decided else 1.0},
+        "actions": np.bincount(acts, minlength=8).tolist(),
+        "exact": "learned value == fixed value on every call",
+    }
+    print(json.dumps(out), flush=True)
+
+
 def summarize_profile(path):
     """Per-kernel duration table from a rocprofv3 kernel-trace output: the
     rocpd SQLite database or the kernel_trace CSV."""
@@ -443,6 +566,7 @@ def main():
     ap.add_argument("--workers", type=int, default=2, help="serving workers (c5)")
     ap.add_argument("--closed-requests", type=int, default=30, help="closed-loop requests (c5)")
     ap.add_argument("--open-requests", type=int, default=100, help="open-loop requests per load (c5)")
+    ap.add_argument("--train-calls", type=int, default=18, help="update calls per training graph (learned20)")
     ap.add_argument("--calibration-copy-mib", type=int, default=0,
                     help="run a float32 negate over this many MiB first (HBM counter calibration)")
     args = ap.parse_args()
@@ -455,6 +579,9 @@ def main():
         return
     if args.config == "c5":
         run_serving(args)
+        return
+    if args.config == "learned20":
+        run_learned(args)
         return
 
     import torch

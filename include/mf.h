@@ -98,6 +98,24 @@ typedef struct {
                                workgroup barriers between its levels or
                                rounds, while the others wait; 0 = 128,
                                < 0 = never                                   */
+    int32_t lazy_items;     /* a BFS level whose frontier holds at least this
+                               many items reads the residual of an arc's
+                               twin (a gather from anywhere in the arc array)
+                               only for heads the BFS has not reached yet,
+                               one dependent load later; smaller levels read
+                               it alongside the head's height; 0 = 1024,
+                               < 0 = never                                   */
+    int32_t bottom_up;      /* direction-optimising global relabel: a BFS
+                               level runs bottom-up (every vertex not reached
+                               yet looks for a parent on the frontier among
+                               its own arcs and stops at the first) when the
+                               frontier's arcs times this number exceed the
+                               arcs of the vertices not reached yet, and
+                               stays bottom-up while the frontier holds at
+                               least 1/24 of the vertices; the levels and
+                               heights are those of the top-down BFS;
+                               0 = 14, < 0 = top-down only (always so with
+                               one workgroup)                                */
     int32_t reserved[1];    /* must be zero                                   */
     /* Device memory of the handle (optional, both or neither): dev_alloc
      * returns `bytes` of device memory on opts.device (aligned to 256 bytes)

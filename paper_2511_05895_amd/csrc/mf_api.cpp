@@ -67,6 +67,8 @@ struct mf_handle {
     int32_t use_gap = 0;
     int32_t stall_rounds = 3;
     int32_t solo_items = 0;
+    int32_t lazy_items = 0;
+    int32_t bu_alpha = 0;  // direction rule of the BFS (0: top-down only)
     int32_t combine = 0;
     double tick_ms = 1e-5;  // one wall-clock tick in ms
     int32_t seq = 1;  // next round id; round ids stamp mark[] and rmark[]
@@ -109,6 +111,11 @@ namespace {
 
 // Default frontier size (items) up to which one workgroup runs BFS levels alone.
 constexpr int32_t kSoloItems = 128;
+constexpr int32_t kLazyItems = 1024;
+// Direction rule of the BFS: bottom-up when frontier arcs x alpha exceed the
+// arcs not reached yet; back to top-down below n / beta frontier vertices.
+constexpr int32_t kBuAlpha = 14;
+constexpr int32_t kBuBeta = 24;
 
 int fail(mf_handle_t *h, int code, const std::string &msg) {
     if (h) h->err = msg;
@@ -206,6 +213,9 @@ mf::LoopParams loop_params(const mf_handle_t *h) {
     p.use_gap = h->use_gap;
     p.stall_rounds = h->stall_rounds;
     p.solo_items = h->solo_items;
+    p.lazy_items = h->lazy_items;
+    p.bu_alpha = h->bu_alpha;
+    p.bu_beta = kBuBeta;
     p.combine = h->combine;
     p.policy_mode = h->policy_mode;
     p.policy_w = mf::policy_device_params(h->policy);
@@ -634,6 +644,7 @@ MF_API int mf_create(const mf_csr_t *g, const int32_t *cap, int32_t s, int32_t t
     h->push_pull = (o.flags & MF_FLAG_PUSH_PULL) ? 1 : 0;
     h->stall_rounds = o.stall_rounds == 0 ? 3 : (o.stall_rounds < 0 ? 0 : o.stall_rounds);
     h->solo_items = o.solo_items == 0 ? kSoloItems : (o.solo_items < 0 ? 0 : o.solo_items);
+    h->lazy_items = o.lazy_items == 0 ? kLazyItems : (o.lazy_items < 0 ? INT32_MAX : o.lazy_items);
     // one cycle per visit: rounds re-queue a vertex that keeps excess, so
     // further cycles in one visit mostly repeat what the next round does
     h->kc = o.kernel_cycles > 0 ? o.kernel_cycles : 1;
@@ -752,6 +763,42 @@ MF_API int mf_create(const mf_csr_t *g, const int32_t *cap, int32_t s, int32_t t
     if (grid > 1 && grid > maxb)
         return bail(MF_EINVAL, "grid_blocks above the co-resident limit " + std::to_string(maxb));
     h->grid = grid;
+    // items of the bottom-up BFS levels (several workgroups only): the first
+    // item of every vertex in vertex order, then the further items of long
+    // lists, all second items first, so that one wavefront's 64 items come
+    // from many vertices
+    if (grid > 1 && o.bottom_up >= 0) {
+        std::vector<int4> items;
+        try {
+            items.reserve((size_t)n + (size_t)(A / mf::kChunk) + 1);
+            std::vector<int32_t> longv;  // vertices with items left after the k-th
+            for (int32_t v = 0; v < n; ++v) {
+                const int32_t b = hp.row_ptr[v], en = hp.row_ptr[v + 1];
+                if (en > b) items.push_back(make_int4(v, b, std::min(en, b + mf::kChunk), 0));
+                if (en - b > mf::kChunk) longv.push_back(v);
+            }
+            for (int32_t k = 1; !longv.empty(); ++k) {
+                size_t keep = 0;
+                for (const int32_t v : longv) {
+                    const int32_t b = hp.row_ptr[v] + k * mf::kChunk, en = hp.row_ptr[v + 1];
+                    items.push_back(make_int4(v, b, std::min(en, b + mf::kChunk), 0));
+                    if (en - b > mf::kChunk) longv[keep++] = v;
+                }
+                longv.resize(keep);
+            }
+        } catch (const std::bad_alloc &) {
+            return bail(MF_ENOMEM, "host allocation failed while building the bottom-up items");
+        }
+        int4 *bi = nullptr;
+        if ((e = dev_alloc(h, &bi, (int64_t)items.size())) != hipSuccess)
+            return bail(MF_ENOMEM, std::string("hipMalloc bu_items: ") + hipGetErrorString(e));
+        if ((e = up(bi, items.data(), sizeof(int4) * items.size())) != hipSuccess ||
+            (e = hipStreamSynchronize(h->stream)) != hipSuccess)
+            return bail(MF_EDEVICE, std::string("upload: ") + hipGetErrorString(e));
+        d.bu_items = bi;
+        d.n_bu_items = (int32_t)items.size();
+        h->bu_alpha = o.bottom_up == 0 ? kBuAlpha : o.bottom_up;
+    }
     if (h->push_pull) {
         // the second view up front: push-pull updates then allocate nothing
         const int rc = ensure_views(h);

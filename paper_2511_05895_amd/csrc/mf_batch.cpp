@@ -485,6 +485,7 @@ MF_API int mf_batch_create(int32_t count, const int32_t *n, const int64_t *m, co
     pr.max_rounds = 65536;
     pr.seq_base = 1;
     pr.rounds_per_level = 1;
+    pr.lazy_items = 1024;
     int rc = apply_config(b);
     if (rc) {
         std::string msg = b->err;

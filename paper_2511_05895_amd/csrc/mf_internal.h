@@ -94,6 +94,8 @@ struct Ctrl {
     PaddedU32 bar_count;  // monotonic barrier arrivals of the launch
     PaddedU32 abort;
     int32_t qcount[4];  // frontier items per BFS level, triple-buffered
+    int32_t qverts[4];  // vertices discovered per BFS level (direction rule), same buffering
+    int64_t qarcs[4];   // their arcs
     ListCtr lst[3];     // active lists of the rounds, triple-buffered
     int32_t nrelab;     // vertices relabelled in the current phase
     int32_t status;
@@ -148,6 +150,12 @@ struct DevGraph {
     int32_t *hcount;    // n+1: vertices at each height below |V| (gap heuristic)
     int32_t *heavy_all; // vertices with long arc lists (topology-driven sweeps)
     int32_t n_heavy_all;
+    // Every vertex's arc list in items of at most kChunk arcs, {vertex, first
+    // arc, end arc, 0}: the first item of every vertex in vertex order, then
+    // the further items of long lists, second items first (bottom-up BFS
+    // levels); null: no bottom-up levels.
+    const int4 *bu_items;
+    int32_t n_bu_items;
     float *ptrace;      // kTraceCap x kPolRec policy-trace records, or null
     Ctrl *ctrl;
     // Optional part tags (null: none).  Only vertices tagged part_want can be
@@ -189,6 +197,12 @@ struct LoopParams {
                                // touching its excess (graphs with vertices of huge degree)
     int32_t no_rie;            // 1: no RemoveInvalidEdges (pushes never exceed the excess, so no
                                // deficit is created; the flow extraction needs that)
+    int32_t lazy_items;        // a BFS level of at least this many frontier items reads an arc's
+                               // twin residual only for heads not reached yet
+    int32_t bu_alpha;          // > 0: a BFS level runs bottom-up when its frontier's arcs times this
+                               // exceed the arcs of the vertices not reached yet, and stays
+                               // bottom-up while the frontier holds at least n / bu_beta vertices
+    int32_t bu_beta;
 };
 
 // Result of one instance of a batched solve.

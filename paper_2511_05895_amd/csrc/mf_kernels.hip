@@ -255,7 +255,7 @@ __device__ void flush_tally(Ctrl *c, Tally &t) {
 // tags, only vertices of the wanted part can be roots, and with part_restrict
 // the heights of the other vertices are left alone.
 template <int SC>
-__device__ void bfs_roots(const DevGraph &g, const Team &tm, bool counts, bool feats, Tally &tl) {
+__device__ void bfs_roots(const DevGraph &g, const Team &tm, bool counts, bool feats, bool track, Tally &tl) {
     const int64_t gtid = tm.tid();
     const int64_t stride = tm.nthreads();
     const int64_t nr = ((int64_t)g.n + 63) & ~63ll;
@@ -278,6 +278,13 @@ __device__ void bfs_roots(const DevGraph &g, const Team &tm, bool counts, bool f
         const int nroot = (int)wave_sum((int64_t)root);
         if (counts && lane_id() == 0 && nroot) add<SC>(&g.hcount[0], nroot);
         if (feats && lane_id() == 0 && nroot) add<SC>(&g.ctrl->feat_reached, nroot);
+        if (track && nroot) {
+            const int64_t ra = wave_sum((int64_t)(end - beg));
+            if (lane_id() == 0) {
+                add<SC>(&g.ctrl->qverts[0], nroot);
+                add<SC>(&g.ctrl->qarcs[0], ra);
+            }
+        }
         const int base = wave_appendn<SC>(&g.ctrl->qcount[0], c);
         for (int j = 0; j < c; ++j)
             g.q[0][base + j] = make_int2(beg + j * kChunk, min(beg + (j + 1) * kChunk, end));
@@ -314,6 +321,7 @@ struct BfsStage {
     int32_t light[kStageCap], heavy[kStageCap];
     int32_t cnt[4];  // items, light, heavy, discovered vertices of this level
     int32_t res[6];  // the level's flush: global bases, then counts, of items, light, heavy
+    int64_t arcs;    // arcs of the vertices this level discovered (direction rule)
 };
 
 // Reserve k slots of an LDS counter if they fit under cap (no partial
@@ -328,6 +336,118 @@ __device__ __forceinline__ int stage_reserve(int32_t *ctr, int k, int cap) {
     }
 }
 
+// Output of one 64-lane BFS step (every lane of the wavefront calls it): a
+// lane that discovered v (disc; its arc range [vbeg, vend) and excess ev)
+// appends v's frontier items for the next level and, when v is active (A of
+// Alg. 1: e > 0 and h < |V|, t excluded), v to the active worklist.  The
+// frontier items, both halves of the active list through one packed 64-bit
+// counter {light, heavy}, and the level's vertex and arc tallies are reserved
+// by one lane, back to back so their round trips overlap, or in the
+// workgroup's stage (st).  counts: per-height vertex counts (gap heuristic);
+// feats: the schedule's features; track: vertices and arcs discovered per
+// level (the direction rule of the BFS).
+template <int SC>
+__device__ __forceinline__ void bfs_emit(const DevGraph &g, int L, bool disc, int v, int vbeg, int vend, int64_t ev,
+                                         bool feats, bool counts, bool track, BfsStage *st, int2 *qout,
+                                         int32_t *qout_count, Tally &tl) {
+    const int lane = lane_id();
+    const int n = g.n;
+    bool active = false;
+    if (disc) {
+        active = (v != g.t) && ev > 0;
+        tl.bfs_v++;
+    } else {
+        vbeg = vend = 0;
+    }
+    if (feats) feature_tally<SC>(g.ctrl, active, ev);
+    const int vdeg = vend - vbeg;
+    const int c = disc ? n_items(vdeg) : 0;
+    const int cincl = wave_incl_scan(c);
+    const int ctotal = __shfl(cincl, 63, 64);
+    const bool light = active && vdeg <= kLightMaxDeg;
+    const bool heavy = active && vdeg > kLightMaxDeg && vdeg <= kHugeDeg;
+    const bool huge = active && vdeg > kHugeDeg;
+    const uint64_t lm = __ballot(light), hm = __ballot(heavy);
+    const int ndisc = counts || feats || track ? __popcll(__ballot(disc)) : 0;
+    const int64_t darcs = track ? wave_sum((int64_t)vdeg) : 0;
+    int qbase = 0, lsb = -1, hsb = -1, qsb = -1;
+    int64_t lbase = 0;
+    if (lane == 63) {
+        const int nl = __popcll(lm), nh = __popcll(hm);
+        if (st) {
+            if (ctotal) qsb = stage_reserve(&st->cnt[0], ctotal, kBfsStageItems);
+            if (nl) lsb = stage_reserve(&st->cnt[1], nl, kStageCap);
+            if (nh) hsb = stage_reserve(&st->cnt[2], nh, kStageCap);
+            if (ndisc) atomicAdd(&st->cnt[3], ndisc);
+            if (darcs) atomicAdd(reinterpret_cast<unsigned long long *>(&st->arcs), (unsigned long long)darcs);
+        } else if (ndisc) {
+            if (counts) add<SC>(&g.hcount[L + 1], ndisc);
+            if (feats) add<SC>(&g.ctrl->feat_reached, ndisc);
+            if (track) {
+                add<SC>(&g.ctrl->qverts[(L + 1) % 3], ndisc);
+                add<SC>(&g.ctrl->qarcs[(L + 1) % 3], darcs);
+            }
+        }
+        if (ctotal && qsb < 0) qbase = fetch_add<SC>(qout_count, ctotal);
+        const int gl = lsb < 0 ? nl : 0, gh = hsb < 0 ? nh : 0;
+        if (gl | gh)
+            lbase = fetch_add<SC>(reinterpret_cast<int64_t *>(&g.ctrl->lst[0]), ((int64_t)gh << 32) | (int64_t)gl);
+    }
+    qbase = __shfl(qbase, 63, 64);
+    lbase = __shfl(lbase, 63, 64);
+    qsb = __shfl(qsb, 63, 64);
+    lsb = __shfl(lsb, 63, 64);
+    hsb = __shfl(hsb, 63, 64);
+    int2 *qdst = qsb < 0 ? qout + qbase : st->items + qsb;
+    const int qb = cincl - c;
+    for (int k = 0; k < c; ++k) qdst[qb + k] = make_int2(vbeg + k * kChunk, min(vbeg + (k + 1) * kChunk, vend));
+    if (light) {
+        if (lsb < 0) g.list[0][(int)(uint32_t)lbase + mask_rank(lm)] = v;
+        else st->light[lsb + mask_rank(lm)] = v;
+    }
+    if (heavy) {
+        if (hsb < 0) g.list[0][n - 1 - ((int)(lbase >> 32) + mask_rank(hm))] = v;
+        else st->heavy[hsb + mask_rank(hm)] = v;
+    }
+    const int su = wave_append1<SC>(&g.ctrl->lst[0].huge, huge);  // rare: hubs only
+    if (huge) g.huge[0][su] = v;
+}
+
+// End of a staged BFS level: one reservation per list for the workgroup's
+// staged output, then a coalesced copy (the stage counters start from zero
+// again).  Every thread of the workgroup calls it.
+template <int SC>
+__device__ void bfs_flush(const DevGraph &g, int L, BfsStage *st, bool counts, bool feats, bool track, int2 *qout,
+                          int32_t *qout_count) {
+    const int n = g.n;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int nq = st->cnt[0], nl = st->cnt[1], nh = st->cnt[2], nd = st->cnt[3];
+        int64_t lb = 0;
+        st->res[0] = nq ? fetch_add<SC>(qout_count, nq) : 0;
+        if (nl | nh)
+            lb = fetch_add<SC>(reinterpret_cast<int64_t *>(&g.ctrl->lst[0]), ((int64_t)nh << 32) | (int64_t)nl);
+        if (nd && counts) add<SC>(&g.hcount[L + 1], nd);
+        if (nd && feats) add<SC>(&g.ctrl->feat_reached, nd);
+        if (nd && track) {
+            add<SC>(&g.ctrl->qverts[(L + 1) % 3], nd);
+            add<SC>(&g.ctrl->qarcs[(L + 1) % 3], st->arcs);
+        }
+        st->res[1] = (int)(uint32_t)lb;
+        st->res[2] = (int)(lb >> 32);
+        st->res[3] = nq;
+        st->res[4] = nl;
+        st->res[5] = nh;
+        st->cnt[0] = st->cnt[1] = st->cnt[2] = st->cnt[3] = 0;
+        st->arcs = 0;
+    }
+    __syncthreads();
+    const int nq = st->res[3], nl = st->res[4], nh = st->res[5];
+    for (int i = threadIdx.x; i < nq; i += blockDim.x) qout[st->res[0] + i] = st->items[i];
+    for (int i = threadIdx.x; i < nl; i += blockDim.x) g.list[0][st->res[1] + i] = st->light[i];
+    for (int i = threadIdx.x; i < nh; i += blockDim.x) g.list[0][n - 1 - (st->res[2] + i)] = st->heavy[i];
+}
+
 // One BFS level, top-down: for every arc (w -> v) of a frontier item, v joins
 // level L+1 when it is unvisited (height |V|), is not s, and has residual
 // capacity toward w (the twin arc v -> w).  Newly reached vertices become
@@ -339,7 +459,7 @@ __device__ __forceinline__ int stage_reserve(int32_t *ctr, int k, int cap) {
 // it.
 template <int SC>
 __device__ void bfs_level(const DevGraph &g, const Team &tm, int L, int cnt, bool feats, bool counts,
-                          BfsStage *st, Tally &tl) {
+                          bool track, bool lazy, BfsStage *st, Tally &tl) {
     const int2 *__restrict__ qin = g.q[L & 1];
     int2 *qout = g.q[(L + 1) & 1];
     int32_t *qout_count = &g.ctrl->qcount[(L + 1) % 3];
@@ -380,14 +500,18 @@ __device__ void bfs_level(const DevGraph &g, const Team &tm, int L, int cnt, boo
             if (j < total) {
                 const int a = obeg + (j - oexcl);
                 // the head and the twin index come in one step, the head's height
-                // and the twin's residual in the next
+                // and the twin's residual in the next; on a large level the
+                // twin's residual (a gather from anywhere in the arc array) is
+                // read only for heads not reached yet
                 const int2 rec = g.arc[a];
                 const int tw = g.twin[a];
                 v = rec.x;
                 const int hv = g.h[v];
-                const int cft = g.arc[tw].y;
+                const bool cand = v != g.s && hv == n;
+                int cft = 1;
+                if (!lazy || cand) cft = g.arc[tw].y;
                 tl.bfs_a++;
-                if (v != g.s && hv == n && cft > 0 && (!g.part_restrict || g.part[v] == g.part_want)) {
+                if (cand && cft > 0 && (!g.part_restrict || g.part[v] == g.part_want)) {
                     // the candidate's row bounds and excess load alongside the
                     // compare-and-swap that decides the discovery
                     vbeg = g.row_ptr[v];
@@ -396,91 +520,89 @@ __device__ void bfs_level(const DevGraph &g, const Team &tm, int L, int cnt, boo
                     disc = cas<SC>(&g.h[v], n, L + 1);
                 }
             }
-            bool active = false;
-            if (disc) {
-                active = (v != g.t) && ev > 0;
-                tl.bfs_v++;
-            } else {
-                vbeg = vend = 0;
-            }
-            if (feats) feature_tally<SC>(g.ctrl, active, ev);
-            const int vdeg = vend - vbeg;
-            // reservations of this step: frontier items, and both halves of
-            // the active list through one packed 64-bit counter {light, heavy};
-            // one lane issues them back to back so their round trips overlap
-            // (or reserves in the workgroup's stage)
-            const int c = disc ? n_items(vdeg) : 0;
-            const int cincl = wave_incl_scan(c);
-            const int ctotal = __shfl(cincl, 63, 64);
-            const bool light = active && vdeg <= kLightMaxDeg;
-            const bool heavy = active && vdeg > kLightMaxDeg && vdeg <= kHugeDeg;
-            const bool huge = active && vdeg > kHugeDeg;
-            const uint64_t lm = __ballot(light), hm = __ballot(heavy);
-            const int ndisc = counts || feats ? __popcll(__ballot(disc)) : 0;
-            int qbase = 0, lsb = -1, hsb = -1, qsb = -1;
-            int64_t lbase = 0;
-            if (lane == 63) {
-                const int nl = __popcll(lm), nh = __popcll(hm);
-                if (st) {
-                    if (ctotal) qsb = stage_reserve(&st->cnt[0], ctotal, kBfsStageItems);
-                    if (nl) lsb = stage_reserve(&st->cnt[1], nl, kStageCap);
-                    if (nh) hsb = stage_reserve(&st->cnt[2], nh, kStageCap);
-                    if (ndisc) atomicAdd(&st->cnt[3], ndisc);
-                } else if (ndisc) {
-                    if (counts) add<SC>(&g.hcount[L + 1], ndisc);
-                    if (feats) add<SC>(&g.ctrl->feat_reached, ndisc);
-                }
-                if (ctotal && qsb < 0) qbase = fetch_add<SC>(qout_count, ctotal);
-                const int gl = lsb < 0 ? nl : 0, gh = hsb < 0 ? nh : 0;
-                if (gl | gh)
-                    lbase = fetch_add<SC>(reinterpret_cast<int64_t *>(&g.ctrl->lst[0]),
-                                          ((int64_t)gh << 32) | (int64_t)gl);
-            }
-            qbase = __shfl(qbase, 63, 64);
-            lbase = __shfl(lbase, 63, 64);
-            qsb = __shfl(qsb, 63, 64);
-            lsb = __shfl(lsb, 63, 64);
-            hsb = __shfl(hsb, 63, 64);
-            int2 *qdst = qsb < 0 ? qout + qbase : st->items + qsb;
-            const int qb = cincl - c;
-            for (int k = 0; k < c; ++k)
-                qdst[qb + k] = make_int2(vbeg + k * kChunk, min(vbeg + (k + 1) * kChunk, vend));
-            if (light) {
-                if (lsb < 0) g.list[0][(int)(uint32_t)lbase + mask_rank(lm)] = v;
-                else st->light[lsb + mask_rank(lm)] = v;
-            }
-            if (heavy) {
-                if (hsb < 0) g.list[0][n - 1 - ((int)(lbase >> 32) + mask_rank(hm))] = v;
-                else st->heavy[hsb + mask_rank(hm)] = v;
-            }
-            const int su = wave_append1<SC>(&g.ctrl->lst[0].huge, huge);  // rare: hubs only
-            if (huge) g.huge[0][su] = v;
+            bfs_emit<SC>(g, L, disc, v, vbeg, vend, ev, feats, counts, track, st, qout, qout_count, tl);
         }
     }
-    if (!st) return;
-    // flush: one reservation per list for the workgroup's staged output, then
-    // a coalesced copy (the stage counters start from zero again)
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const int nq = st->cnt[0], nl = st->cnt[1], nh = st->cnt[2], nd = st->cnt[3];
-        int64_t lb = 0;
-        st->res[0] = nq ? fetch_add<SC>(qout_count, nq) : 0;
-        if (nl | nh)
-            lb = fetch_add<SC>(reinterpret_cast<int64_t *>(&g.ctrl->lst[0]), ((int64_t)nh << 32) | (int64_t)nl);
-        if (nd && counts) add<SC>(&g.hcount[L + 1], nd);
-        if (nd && feats) add<SC>(&g.ctrl->feat_reached, nd);
-        st->res[1] = (int)(uint32_t)lb;
-        st->res[2] = (int)(lb >> 32);
-        st->res[3] = nq;
-        st->res[4] = nl;
-        st->res[5] = nh;
-        st->cnt[0] = st->cnt[1] = st->cnt[2] = st->cnt[3] = 0;
+    if (st) bfs_flush<SC>(g, L, st, counts, feats, track, qout, qout_count);
+}
+
+// One BFS level, bottom-up (the direction-optimising BFS): every vertex v
+// not reached yet (height |V|, not s) looks through its own arcs (v -> w)
+// for one with residual capacity whose head w is on level L, and joins level
+// L+1 at the first it finds.  The same vertices join the level as in the
+// top-down step, but only v's own arc records and the heads' heights are
+// read (no gather of twin residuals), and a vertex stops at its first
+// parent.  The team walks the static item list g.bu_items: a wavefront takes
+// 64 items and runs through their remaining arcs 64 at a time (load-balanced
+// scan), dropping an item as soon as its vertex has a parent.  Several items
+// of one long list can find parents at once; the compare-and-swap on the
+// height makes one of them the discovery.  Output as in the top-down step.
+// Every thread of the workgroup calls it.
+template <int SC>
+__device__ void bfs_bottom_up(const DevGraph &g, const Team &tm, int L, bool feats, bool counts, BfsStage *st,
+                              Tally &tl) {
+    int2 *qout = g.q[(L + 1) & 1];
+    int32_t *qout_count = &g.ctrl->qcount[(L + 1) % 3];
+    const int lane = lane_id();
+    const int n = g.n;
+    const int64_t nb = g.n_bu_items;
+    const int64_t nwaves = tm.nwaves();
+    for (int64_t base = tm.wave() * 64; base < nb; base += nwaves * 64) {
+        const int64_t idx = base + lane;
+        int v = -1, beg = 0, len = 0;
+        if (idx < nb) {
+            const int4 it = g.bu_items[idx];
+            if (it.x != g.s && g.h[it.x] == n) {
+                v = it.x;
+                beg = it.y;
+                len = it.z - it.y;
+            }
+        }
+        bool disc = false;
+        for (;;) {
+            const int incl = wave_incl_scan(len);
+            const int total = __shfl(incl, 63, 64);
+            if (total == 0) break;
+            const int excl = incl - len;
+            // largest lane o with excl[o] <= lane (that lane still has arcs)
+            int o = 0;
+#pragma unroll
+            for (int step = 32; step >= 1; step >>= 1) {
+                const int cand = o + step;
+                const int ex = __shfl(excl, cand, 64);
+                if (ex <= lane) o = cand;
+            }
+            const int obeg = __shfl(beg, o, 64);
+            const int oexcl = __shfl(excl, o, 64);
+            bool hit = false;
+            if (lane < total) {
+                const int2 r = g.arc[obeg + (lane - oexcl)];
+                if (r.y > 0) hit = g.h[r.x] == L;
+                tl.bfs_a++;
+            }
+            const uint64_t hm = __ballot(hit);
+            // this lane's item owns the step's arcs [lo, hi)
+            const int lo = min(excl, 64), hi = min(incl, 64);
+            const int used = hi - lo;
+            const bool found = used > 0 && ((hm >> lo) & (used == 64 ? ~0ull : ((1ull << used) - 1))) != 0;
+            if (found) {
+                len = 0;
+                disc = cas<SC>(&g.h[v], n, L + 1);
+            } else {
+                beg += used;
+                len -= used;
+            }
+        }
+        int vbeg = 0, vend = 0;
+        int64_t ev = 0;
+        if (disc) {
+            vbeg = g.row_ptr[v];
+            vend = g.row_ptr[v + 1];
+            ev = g.e[v];
+        }
+        bfs_emit<SC>(g, L, disc, v, vbeg, vend, ev, feats, counts, true, st, qout, qout_count, tl);
     }
-    __syncthreads();
-    const int nq = st->res[3], nl = st->res[4], nh = st->res[5];
-    for (int i = threadIdx.x; i < nq; i += blockDim.x) qout[st->res[0] + i] = st->items[i];
-    for (int i = threadIdx.x; i < nl; i += blockDim.x) g.list[0][st->res[1] + i] = st->light[i];
-    for (int i = threadIdx.x; i < nh; i += blockDim.x) g.list[0][n - 1 - (st->res[2] + i)] = st->heavy[i];
+    if (st) bfs_flush<SC>(g, L, st, counts, feats, true, qout, qout_count);
 }
 
 // ---------------------------------------------------------------------------
@@ -1222,24 +1344,45 @@ __device__ void solve_loop(const DevGraph &g, const Team &tm, const LoopParams &
         // the BFS tallies the schedule's features only where a decision uses
         // them: every phase, or the first phase of a call decided per call
         const bool feats = policy && !(p.policy_per_call && iter > 0);
-        bfs_roots<SC>(g, tm, counts, feats, tl);
+        // direction rule of the BFS (direction-optimising BFS): a level runs
+        // bottom-up when its frontier's arcs are a large share of the arcs of
+        // the vertices not reached yet, and stays so while the frontier is
+        // large; small and restricted BFS passes stay top-down
+        const bool dir = p.bu_alpha > 0 && g.bu_items != nullptr && !g.part_restrict;
+        bfs_roots<SC>(g, tm, counts, feats, dir, tl);
         if (!grid_barrier(c, tm, bar_epoch, p.barrier_ticks)) return;
         int L = 0;
+        bool bu = false;
+        int64_t seen_arcs = 0;  // arcs of the vertices reached so far
         for (;;) {
             const int cnt = uniform(ld<SC>(&c->qcount[L % 3]));
             if (cnt == 0) break;
+            if (dir) {
+                const int64_t fa = uniform(ld<SC>(&c->qarcs[L % 3]));
+                const int fv = uniform(ld<SC>(&c->qverts[L % 3]));
+                seen_arcs += fa;
+                bu = bu ? (int64_t)fv * p.bu_beta >= g.n : fa * p.bu_alpha > (int64_t)g.A - seen_arcs;
+            }
             // A small frontier is expanded by the first workgroup alone, level
             // after level with workgroup barriers in between (no grid barrier,
             // no L2 invalidation), while the others wait at the next grid
             // barrier.  The stretch ends at a level with no item or more than
             // solo_items items, or after a quarter of the barrier's wait limit.
-            const bool alone = tm.size > 1 && cnt <= p.solo_items;
+            const bool alone = !bu && tm.size > 1 && cnt <= p.solo_items;
             if (!alone || tm.rank == 0) {
                 const Team bt = alone ? Team{0, 1} : tm;
                 const uint64_t ts = wall_clock64();
                 for (int k = cnt;;) {
-                    if (threadIdx.x == 0 && tm.rank == 0) c->qcount[(L + 2) % 3] = 0;
-                    bfs_level<SC>(g, bt, L, k, feats, counts, !alone && k >= kBfsStageMin ? stage : nullptr, tl);
+                    if (threadIdx.x == 0 && tm.rank == 0) {
+                        c->qcount[(L + 2) % 3] = 0;
+                        c->qverts[(L + 2) % 3] = 0;
+                        c->qarcs[(L + 2) % 3] = 0;
+                    }
+                    if (bu)
+                        bfs_bottom_up<SC>(g, bt, L, feats, counts, stage, tl);
+                    else
+                        bfs_level<SC>(g, bt, L, k, feats, counts, dir, k >= p.lazy_items,
+                                      !alone && k >= kBfsStageMin ? stage : nullptr, tl);
                     if (!alone) break;
                     __syncthreads();
                     ++L;
@@ -1401,9 +1544,11 @@ __device__ void solve_loop(const DevGraph &g, const Team &tm, const LoopParams &
         if (leader) {
             add<SC>(&c->stat[kStPrTicks], (int64_t)(tr - tp));
             add<SC>(&c->stat[kStRieTicks], (int64_t)(wall_clock64() - tr));
-            c->qcount[0] = 0;
-            c->qcount[1] = 0;
-            c->qcount[2] = 0;
+            for (int k = 0; k < 3; ++k) {
+                c->qcount[k] = 0;
+                c->qverts[k] = 0;
+                c->qarcs[k] = 0;
+            }
             c->feat_reached = 0;  // counted from the next phase's roots on
             c->rounds += r + 1;
             add<SC>(&c->stat[kStIterations], 1);
@@ -1443,6 +1588,7 @@ __global__ void __launch_bounds__(BLOCK) k_loop(DevGraph g, LoopParams p) {
         __shared__ BfsStage s_stage;
         __shared__ Combine s_comb;
         if (threadIdx.x < 4) s_stage.cnt[threadIdx.x] = 0;
+        if (threadIdx.x == 0) s_stage.arcs = 0;
         for (int i = threadIdx.x; i < kCombine; i += blockDim.x) {
             s_comb.key[i] = -1;
             s_comb.sum[i] = 0;
@@ -1466,6 +1612,7 @@ __global__ void __launch_bounds__(BLOCK)
     __shared__ BfsStage s_stage;
     __shared__ Combine s_comb;
     if (threadIdx.x < 4) s_stage.cnt[threadIdx.x] = 0;
+    if (threadIdx.x == 0) s_stage.arcs = 0;
     for (int i = threadIdx.x; i < kCombine; i += blockDim.x) {
         s_comb.key[i] = -1;
         s_comb.sum[i] = 0;
@@ -1999,5 +2146,6 @@ hipError_t launch_fill_i32(int32_t *p, int64_t count, int32_t value, hipStream_t
     hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(count, 256)), dim3(256), 0, st, p, count, value);
     return hipGetLastError();
 }
+
 
 }  // namespace mf

@@ -40,7 +40,8 @@ class mf_opts_t(C.Structure):
                 ("device", C.c_int32), ("max_iterations", C.c_int64), ("time_budget_ms", C.c_int32),
                 ("max_rounds", C.c_int32), ("relabel_budget", C.c_int32), ("rounds_per_level", C.c_int32),
                 ("flags", C.c_int32), ("stall_rounds", C.c_int32), ("solo_items", C.c_int32),
-                ("reserved", C.c_int32 * 1), ("dev_alloc", ALLOC_FN), ("dev_free", FREE_FN),
+                ("lazy_items", C.c_int32),
+                ("bottom_up", C.c_int32), ("reserved", C.c_int32 * 1), ("dev_alloc", ALLOC_FN), ("dev_free", FREE_FN),
                 ("alloc_ctx", C.c_void_p)]
 
 
@@ -369,7 +370,8 @@ class MaxFlow:
 
     def __init__(self, g, kernel_cycles=0, mode=MF_MODE_DATA, grid_blocks=0, max_iterations=-1,
                  device=0, cap=None, time_budget_ms=0, max_rounds=0, relabel_budget=0,
-                 rounds_per_level=0, flags=0, stall_rounds=0, solo_items=0, allocator=None):
+                 rounds_per_level=0, flags=0, stall_rounds=0, solo_items=0, lazy_items=0, bottom_up=0,
+                 allocator=None):
         """allocator: optional object with alloc(nbytes) -> device address (0
         on failure) and free(address); the handle's device memory then comes
         from it (e.g. TorchAllocator)."""
@@ -381,6 +383,8 @@ class MaxFlow:
                                FREE_FN(lambda ptr, ctx: allocator.free(int(ptr))))
             o.dev_alloc, o.dev_free = self._alloc_cbs
         o.solo_items = solo_items
+        o.lazy_items = lazy_items
+        o.bottom_up = bottom_up
         o.time_budget_ms = time_budget_ms
         o.max_rounds = max_rounds
         o.relabel_budget = relabel_budget
