@@ -150,6 +150,12 @@ typedef struct {
  * solved, no active vertex and no residual arc from the source side to the
  * sink side.  A failed check returns MF_EDEVICE naming it. */
 #define MF_FLAG_DEBUG_CHECKS 4
+/* opts.flags: visit vertices of more than 32 arcs with the cycle of Alg. 2
+ * as written (a scan of the whole arc list for the lowest residual neighbour
+ * height, then pushes to the arcs at that height or a relabel) instead of the
+ * default walk, which pushes downhill in arc order, stops once the excess is
+ * gone and scans the whole list only to relabel.  Results are the same. */
+#define MF_FLAG_SCAN_FIRST 8
 
 /* Counters of the last mf_solve / mf_apply_updates* / mf_resume call. */
 typedef struct {

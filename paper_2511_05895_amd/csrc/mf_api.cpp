@@ -69,6 +69,7 @@ struct mf_handle {
     int32_t solo_items = 0;
     int32_t lazy_items = 0;
     int32_t bu_alpha = 0;  // direction rule of the BFS (0: top-down only)
+    int32_t walk = 1;      // long arc lists visited by the downhill walk (else scan first)
     int32_t combine = 0;
     double tick_ms = 1e-5;  // one wall-clock tick in ms
     int32_t seq = 1;  // next round id; round ids stamp mark[] and rmark[]
@@ -98,6 +99,9 @@ struct mf_handle {
     int32_t *d_rem = nullptr;
     int32_t *d_eflow = nullptr;
     mf::Ctrl *h_vctrl = nullptr;  // pinned read-back of the two views' control blocks
+    mf::DevGraph *d_tviews = nullptr;     // the two-team kernel's table of views
+    mf::LoopParams *d_tparams = nullptr;  // and of their loop parameters
+    unsigned char *h_tdesc = nullptr;     // pinned staging of both tables
     int32_t vseq = 1;             // next round id of rv's marks
     bool teams_fit = false;       // the two-team kernel's grid fits the device at once
     State state = State::NoFlow;
@@ -172,6 +176,7 @@ void release(mf_handle_t *h) {
     raw_free(h, h->d_ptrace);
     if (h->h_ctrl) (void)hipHostFree(h->h_ctrl);
     if (h->h_vctrl) (void)hipHostFree(h->h_vctrl);
+    if (h->h_tdesc) (void)hipHostFree(h->h_tdesc);
     for (auto &e : h->ev)
         if (e) (void)hipEventDestroy(e);
     if (h->own_stream) (void)hipStreamDestroy(h->own_stream);
@@ -216,6 +221,7 @@ mf::LoopParams loop_params(const mf_handle_t *h) {
     p.lazy_items = h->lazy_items;
     p.bu_alpha = h->bu_alpha;
     p.bu_beta = kBuBeta;
+    p.walk = h->walk;
     p.combine = h->combine;
     p.policy_mode = h->policy_mode;
     p.policy_w = mf::policy_device_params(h->policy);
@@ -390,12 +396,17 @@ int ensure_views(mf_handle_t *h) {
     VALLOC(f.ctrl, 1);
     VALLOC(h->d_rem, A);
     VALLOC(h->d_eflow, m);
+    VALLOC(h->d_tviews, 2);
+    VALLOC(h->d_tparams, 2);
 #undef VALLOC
     r.ptrace = nullptr;
     f.ptrace = nullptr;
     if (!h->h_vctrl &&
         hipHostMalloc((void **)&h->h_vctrl, 2 * sizeof(mf::Ctrl), hipHostMallocDefault) != hipSuccess)
         return fail(h, MF_ENOMEM, "pinned control blocks of the views");
+    if (!h->h_tdesc && hipHostMalloc((void **)&h->h_tdesc, 2 * (sizeof(mf::DevGraph) + sizeof(mf::LoopParams)),
+                                     hipHostMallocDefault) != hipSuccess)
+        return fail(h, MF_ENOMEM, "pinned staging of the views' table");
     HIP_TRY(h, mf::launch_fill_i32(r.mark, n, 0, h->stream));
     HIP_TRY(h, mf::launch_fill_i32(r.rmark, n, 0, h->stream));
     int tmax = 0;
@@ -434,7 +445,22 @@ int run_two_views(mf_handle_t *h, const mf::DevGraph &a, mf::LoopParams pa, int3
     if (pa.use_gap) HIP_TRY(h, mf::launch_fill_i32(ga.hcount, (int64_t)ga.n + 1, 0, h->stream));
     if (pb.use_gap) HIP_TRY(h, mf::launch_fill_i32(gb.hcount, (int64_t)gb.n + 1, 0, h->stream));
     if (h->teams_fit) {
-        HIP_TRY(h, mf::launch_teams(ga, pa, gb, pb, h->d_work, h->grid, h->stream));
+        // the table of both views and their parameters (the last call's
+        // copies are done: every call ends with a stream synchronisation)
+        mf::DevGraph *tv = reinterpret_cast<mf::DevGraph *>(h->h_tdesc);
+        mf::LoopParams *tp = reinterpret_cast<mf::LoopParams *>(h->h_tdesc + 2 * sizeof(mf::DevGraph));
+        tv[0] = ga;
+        tv[1] = gb;
+        tp[0] = pa;
+        tp[1] = pb;
+        hipError_t le = hipMemcpyAsync(h->d_tviews, tv, 2 * sizeof(mf::DevGraph), hipMemcpyHostToDevice, h->stream);
+        if (le == hipSuccess)
+            le = hipMemcpyAsync(h->d_tparams, tp, 2 * sizeof(mf::LoopParams), hipMemcpyHostToDevice, h->stream);
+        if (le == hipSuccess) le = mf::launch_teams(h->d_tviews, h->d_tparams, pa.walk != 0, h->d_work, h->grid, h->stream);
+        if (le != hipSuccess) {
+            (void)hipStreamSynchronize(h->stream);  // the staging is free again for the next call
+            return hip_fail(h, le, "two-team launch");
+        }
     } else {  // one workgroup (or a grid the two-team kernel cannot hold): one side after the other
         HIP_TRY(h, mf::launch_loop(ga, pa, h->grid, h->stream));
         HIP_TRY(h, mf::launch_loop(gb, pb, h->grid, h->stream));
@@ -573,7 +599,10 @@ bool opts_valid(const mf_opts_t &o, std::string *why) {
     if (o.time_budget_ms < 0) { *why = "time_budget_ms must be >= 0"; return false; }
     if (o.max_rounds < 0) { *why = "max_rounds must be >= 0"; return false; }
     if (o.relabel_budget < 0) { *why = "relabel_budget must be >= 0"; return false; }
-    if (o.flags & ~(MF_FLAG_GAP | MF_FLAG_PUSH_PULL | MF_FLAG_DEBUG_CHECKS)) { *why = "unknown flags"; return false; }
+    if (o.flags & ~(MF_FLAG_GAP | MF_FLAG_PUSH_PULL | MF_FLAG_DEBUG_CHECKS | MF_FLAG_SCAN_FIRST)) {
+        *why = "unknown flags";
+        return false;
+    }
     if (!o.dev_alloc != !o.dev_free) { *why = "dev_alloc and dev_free go together"; return false; }
     if (o.reserved[0]) { *why = "reserved fields must be zero"; return false; }
     return true;
@@ -642,6 +671,7 @@ MF_API int mf_create(const mf_csr_t *g, const int32_t *cap, int32_t s, int32_t t
     h->rounds_per_level = o.rounds_per_level == 0 ? 1 : (o.rounds_per_level < 0 ? 0 : o.rounds_per_level);
     h->use_gap = (o.flags & MF_FLAG_GAP) ? 1 : 0;
     h->push_pull = (o.flags & MF_FLAG_PUSH_PULL) ? 1 : 0;
+    h->walk = (o.flags & MF_FLAG_SCAN_FIRST) ? 0 : 1;
     h->stall_rounds = o.stall_rounds == 0 ? 3 : (o.stall_rounds < 0 ? 0 : o.stall_rounds);
     h->solo_items = o.solo_items == 0 ? kSoloItems : (o.solo_items < 0 ? 0 : o.solo_items);
     h->lazy_items = o.lazy_items == 0 ? kLazyItems : (o.lazy_items < 0 ? INT32_MAX : o.lazy_items);

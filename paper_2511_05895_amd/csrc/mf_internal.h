@@ -203,6 +203,8 @@ struct LoopParams {
                                // exceed the arcs of the vertices not reached yet, and stays
                                // bottom-up while the frontier holds at least n / bu_beta vertices
     int32_t bu_beta;
+    int32_t walk;              // 1: long arc lists are visited by a walk that pushes downhill in arc
+                               // order and stops when the excess is gone (full scan only to relabel)
 };
 
 // Result of one instance of a batched solve.
@@ -243,10 +245,12 @@ hipError_t launch_adam(float *theta, const float *grad, float *m, float *v, int 
 // Largest co-resident workgroup count of the loop kernel.
 hipError_t loop_max_coresident(int device, int *blocks);
 // Two solve loops side by side in one cooperative launch of `grid` (>= 2)
-// workgroups, split by the arc counts work[0] (view a) and work[1] (view b);
-// the views must touch disjoint vertices and arc pairs.
-hipError_t launch_teams(const DevGraph &ga, const LoopParams &pa, const DevGraph &gb, const LoopParams &pb,
-                        const int64_t *work, int grid, hipStream_t st);
+// workgroups, split by the arc counts work[0] (view 0) and work[1] (view 1);
+// d_views / d_params: device tables of the two views and their loop
+// parameters (both with the same walk setting).  The views must touch
+// disjoint vertices and arc pairs.
+hipError_t launch_teams(const DevGraph *d_views, const LoopParams *d_params, bool walk, const int64_t *work,
+                        int grid, hipStream_t st);
 hipError_t teams_max_coresident(int device, int *blocks);
 // part[v] = T if h(v) < |V| else S; work[0] += arcs of S, work[1] += arcs of T.
 hipError_t launch_part_from_heights(const DevGraph &g, uint8_t *part, int64_t *work, hipStream_t st);

@@ -870,6 +870,91 @@ __device__ int discharge_group(const DevGraph &g, int u, int kc, const RoundCtx 
     return gl == 0 ? relabels : 0;
 }
 
+// A wavefront visits vertex u by walking its arcs in arc order, 64 at a
+// time: the residual arcs that go downhill (head below u) take the excess in
+// arc order (prefix sum of their residual capacities over the wavefront) and
+// the walk stops as soon as the excess is gone; only when it reaches the end
+// of the list with excess left does u relabel, to one above the lowest head
+// among the arcs still residual.  Under exact labels the downhill arcs are
+// those at h(u) - 1, the lowest residual heights, so this is the push of
+// Alg. 2 without the full scan for the minimum before it; a head that a racy
+// relabel left steep is pushed to like any downhill head.  Every lane of the
+// wavefront calls it with the same u (u < 0: idle).  Returns relabels (lane 0).
+template <int SC>
+__device__ int discharge_walk(const DevGraph &g, int u, int kc, const RoundCtx &rc, Tally &tl, int64_t &to_t) {
+    const int lane = lane_id();
+    if (u < 0) return 0;
+    const int n = g.n;
+    const int beg = g.row_ptr[u], end = g.row_ptr[u + 1];
+    int hu = g.h[u];
+    int32_t stamp = g.rmark[u];
+    int relabels = 0;
+    if (rc.use_gap && hu < n && hu > ld<SC>(&g.ctrl->gap)) {  // above a gap: cut off
+        if (lane == 0) {
+            add<SC>(&g.hcount[hu], -1);
+            g.h[u] = n;
+        }
+        hu = n;
+    }
+    int64_t eu = 0;
+    if (lane == 0) eu = ld<SC>(&g.e[u]);
+    eu = __shfl(eu, 0, 64);
+    for (int cyc = 0; cyc < kc && hu < n; ++cyc) {
+        if (eu <= 0) break;
+        if (lane == 0) tl.pr_cyc++;
+        const int64_t e0 = eu;  // what this walk hands out
+        int64_t sent = 0, now = eu;
+        int hrest = INT32_MAX;  // lowest head among the arcs left residual
+        int walked = 0;
+        for (int base = beg; base < end && sent < e0; base += 64) {
+            const int a = base + lane;
+            int64_t c = 0;
+            int v = -1, hv = INT32_MAX;
+            if (a < end) {
+                const int2 r = g.arc[a];
+                if (r.y > 0) {
+                    hv = g.h[r.x];
+                    if (hv < hu) {
+                        c = max(0, ld<SC>(cf_ptr(g.arc, a)));
+                        v = r.x;
+                    }
+                }
+            }
+            walked += min(64, end - base);
+            const int64_t incl = wave_incl_scan64(c);
+            const int64_t room = e0 - sent;
+            const int64_t excl = incl - c;
+            const int64_t d = (c > 0 && excl < room) ? min(c, room - excl) : 0;
+            const int64_t tot = min(__shfl(incl, 63, 64), room);
+            if (lane == 0 && tot > 0) now = fetch_add<SC>(&g.e[u], -tot) - tot;
+            if (d > 0) {
+                push_arc<SC>(g, rc, a, g.twin[a], v, (int32_t)d, to_t, tl);
+                tl.push++;
+            }
+            if (d < c || (v < 0 && hv != INT32_MAX)) hrest = min(hrest, hv);
+            sent += tot;
+        }
+        if (lane == 0) tl.pr_a += walked;
+        eu = __shfl(now, 0, 64);
+        if (sent >= e0) continue;  // the excess went downhill
+        // the walk reached the end of the list with excess left: relabel
+        if (eu <= 0) break;
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) hrest = min(hrest, __shfl_xor(hrest, d, 64));
+        if (hrest == INT32_MAX) break;  // no residual arc left
+        int hn = 0;
+        if (lane == 0) {
+            hn = relabel_to<SC>(g, u, hu, hrest, rc.use_gap);
+            tl.relabel++;
+            note_relabel<SC>(g, rc, u, stamp);
+        }
+        hu = __shfl(hn, 0, 64);
+        relabels++;
+    }
+    if (lane == 0 && hu < n && eu > 0) list_add<SC>(g, rc, u);
+    return lane == 0 ? relabels : 0;
+}
+
 // Lanes per vertex with a short arc list (at most kLightMaxDeg arcs): the
 // arcs of a typical vertex load in one step instead of one after another.
 constexpr int kLightGroup = 8;
@@ -989,6 +1074,110 @@ __device__ int discharge_block(const DevGraph &g, int u, int kc, const RoundCtx 
     return t == 0 ? relabels : 0;
 }
 
+// The walk of discharge_walk done by a whole workgroup (vertices of more than
+// kHugeDeg arcs): one step covers blockDim.x arcs, the downhill residual
+// capacities are prefix-summed over the workgroup (wavefront scans, then the
+// wavefront totals through LDS), and the walk stops at the step where the
+// excess runs out.  Only a walk that reaches the end of the list relabels.
+// Every thread of the workgroup calls it with the same u; all decisions are
+// uniform.
+template <int SC>
+__device__ int discharge_block_walk(const DevGraph &g, int u, int kc, const RoundCtx &rc, Tally &tl,
+                                    int64_t &to_t) {
+    __shared__ int64_t s_wsum[32];
+    __shared__ int s_wmin[32];
+    __shared__ int64_t s_now;
+    __shared__ int s_h;
+    const int t = threadIdx.x, lane = lane_id(), w = t >> 6, nw = blockDim.x >> 6;
+    const int n = g.n;
+    const int beg = g.row_ptr[u], end = g.row_ptr[u + 1];
+    int hu = g.h[u];
+    int32_t stamp = g.rmark[u];
+    int relabels = 0;
+    if (rc.use_gap && hu < n && hu > ld<SC>(&g.ctrl->gap)) {  // above a gap: cut off
+        if (t == 0) {
+            add<SC>(&g.hcount[hu], -1);
+            g.h[u] = n;
+        }
+        hu = n;
+    }
+    if (t == 0) s_now = ld<SC>(&g.e[u]);
+    __syncthreads();
+    int64_t eu = s_now;
+    for (int cyc = 0; cyc < kc && hu < n; ++cyc) {
+        if (eu <= 0) break;
+        if (t == 0) tl.pr_cyc++;
+        const int64_t e0 = eu;
+        int64_t sent = 0;
+        int hrest = INT32_MAX;
+        int walked = 0;
+        for (int base = beg; base < end && sent < e0; base += blockDim.x) {
+            const int a = base + t;
+            int64_t c = 0;
+            int v = -1, hv = INT32_MAX;
+            if (a < end) {
+                const int2 r = g.arc[a];
+                if (r.y > 0) {
+                    hv = g.h[r.x];
+                    if (hv < hu) {
+                        c = max(0, ld<SC>(cf_ptr(g.arc, a)));
+                        v = r.x;
+                    }
+                }
+            }
+            walked += min((int)blockDim.x, end - base);
+            const int64_t incl = wave_incl_scan64(c);
+            if (lane == 63) s_wsum[w] = incl;
+            __syncthreads();
+            int64_t woff = 0, btot = 0;
+            for (int k = 0; k < nw; ++k) {
+                const int64_t x = s_wsum[k];
+                if (k < w) woff += x;
+                btot += x;
+            }
+            __syncthreads();
+            const int64_t room = e0 - sent;
+            const int64_t excl = woff + incl - c;
+            const int64_t d = (c > 0 && excl < room) ? min(c, room - excl) : 0;
+            if (d > 0) {
+                push_arc<SC>(g, rc, a, g.twin[a], v, (int32_t)d, to_t, tl);
+                tl.push++;
+            }
+            if (d < c || (v < 0 && hv != INT32_MAX)) hrest = min(hrest, hv);
+            sent += min(btot, room);
+        }
+        if (t == 0) {
+            tl.pr_a += walked;
+            if (sent > 0) add<SC>(&g.e[u], -sent);
+        }
+        __syncthreads();
+        if (t == 0) s_now = ld<SC>(&g.e[u]);
+        __syncthreads();
+        eu = s_now;
+        if (sent >= e0) continue;  // the excess went downhill
+        if (eu <= 0) break;
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) hrest = min(hrest, __shfl_xor(hrest, d, 64));
+        if (lane == 0) s_wmin[w] = hrest;
+        __syncthreads();
+        int hmin = INT32_MAX;
+        for (int k = 0; k < nw; ++k) hmin = min(hmin, s_wmin[k]);
+        __syncthreads();
+        if (hmin == INT32_MAX) break;  // no residual arc left
+        if (t == 0) {
+            s_h = relabel_to<SC>(g, u, hu, hmin, rc.use_gap);
+            tl.relabel++;
+            note_relabel<SC>(g, rc, u, stamp);
+        }
+        __syncthreads();
+        hu = s_h;
+        __syncthreads();
+        relabels++;
+    }
+    if (t == 0 && hu < n && eu > 0) list_add<SC>(g, rc, u);
+    return t == 0 ? relabels : 0;
+}
+
 // Excess pushed into t by the lanes of a wavefront, added with one atomic
 // (topology-driven rounds; data-driven rounds sum per workgroup).
 template <int SC>
@@ -1057,7 +1246,7 @@ __device__ void flush_combine(const DevGraph &g, const RoundCtx &rc, Tally &tl) 
 
 // One data-driven round over list rd: short lists by lane, long ones by
 // wavefronts that take the next vertex from a shared counter.
-template <int SC>
+template <int SC, bool WALK>
 __device__ void pr_round(const DevGraph &g, const Team &tm, int rd, int nl, int nh, int nu, int kc,
                          const RoundCtx &rc0, Combine *comb, Tally &tl) {
     const int64_t gtid = tm.tid();
@@ -1095,13 +1284,17 @@ __device__ void pr_round(const DevGraph &g, const Team &tm, int rd, int nl, int 
             const int idx = s_idx;
             __syncthreads();
             if (idx >= nu) break;
-            rl += discharge_block<SC>(g, hl[idx], kc, rc, tl, to_t);
+            if constexpr (WALK) rl += discharge_block_walk<SC>(g, hl[idx], kc, rc, tl, to_t);
+            else rl += discharge_block<SC>(g, hl[idx], kc, rc, tl, to_t);
         }
     }
     // long arc lists: one wavefront per vertex, dealt out round-robin (no
     // shared counter for thousands of wavefronts to contend on)
-    for (int64_t i = tm.wave(); i < nh; i += tm.nwaves())
-        rl += discharge_group<SC, 64>(g, lst[g.n - 1 - i], kc, rc, tl, to_t);
+    for (int64_t i = tm.wave(); i < nh; i += tm.nwaves()) {
+        const int u = lst[g.n - 1 - i];
+        if constexpr (WALK) rl += discharge_walk<SC>(g, u, kc, rc, tl, to_t);
+        else rl += discharge_group<SC, 64>(g, u, kc, rc, tl, to_t);
+    }
     if (comb) flush_combine<SC>(g, rc, tl);
     // the round's counters: summed over the workgroup, one atomic each
     {
@@ -1305,7 +1498,7 @@ __device__ int policy_decide(const DevGraph &g, const LoopParams &p, Ctrl *c, in
 // The persistent solve loop (Alg. 1 / Alg. 4 while-loop)
 // ---------------------------------------------------------------------------
 
-template <int SC>
+template <int SC, bool WALK>
 __device__ void solve_loop(const DevGraph &g, const Team &tm, const LoopParams &p, BfsStage *stage,
                            Combine *comb) {
     Ctrl *c = g.ctrl;
@@ -1491,7 +1684,7 @@ __device__ void solve_loop(const DevGraph &g, const Team &tm, const LoopParams &
                     const RoundCtx rc{g.list[wr], g.huge[wr], nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
                                       nullptr, &c->lst[wr], rbase + r + 1, rbase, p.use_gap != 0};
                     if (topology) pr_round_topology<SC>(g, rt, p.kc, rc, tl);
-                    else pr_round<SC>(g, rt, rd, nl, nh, nu, p.kc, rc, p.combine ? comb : nullptr, tl);
+                    else pr_round<SC, WALK>(g, rt, rd, nl, nh, nu, p.kc, rc, p.combine ? comb : nullptr, tl);
                     ++r;
                     if (!alone) break;
                     __syncthreads();
@@ -1580,7 +1773,9 @@ __device__ void solve_loop(const DevGraph &g, const Team &tm, const LoopParams &
 }
 
 // The whole grid is one team (cooperative launch), or a single workgroup.
-template <int BLOCK, int SC>
+// WALK: long arc lists are visited by the downhill walk (else scan first);
+// the two are separate instances, since both inlined side by side would spill.
+template <int BLOCK, int SC, bool WALK>
 __global__ void __launch_bounds__(BLOCK) k_loop(DevGraph g, LoopParams p) {
     BfsStage *stage = nullptr;
     Combine *comb = nullptr;
@@ -1597,7 +1792,7 @@ __global__ void __launch_bounds__(BLOCK) k_loop(DevGraph g, LoopParams p) {
         stage = &s_stage;
         comb = &s_comb;
     }
-    solve_loop<SC>(g, Team{(int)blockIdx.x, (int)gridDim.x}, p, stage, comb);
+    solve_loop<SC, WALK>(g, Team{(int)blockIdx.x, (int)gridDim.x}, p, stage, comb);
 }
 
 // Two teams in one cooperative launch: workgroups [0, split) run the solve
@@ -1606,9 +1801,9 @@ __global__ void __launch_bounds__(BLOCK) k_loop(DevGraph g, LoopParams p) {
 // and vertices (the S and T sides of a cut with no residual arc from S to
 // T).  split follows the arc counts work[0] (view a) and work[1] (view b),
 // at least one workgroup each.
-template <int BLOCK>
+template <int BLOCK, bool WALK>
 __global__ void __launch_bounds__(BLOCK)
-    k_teams(DevGraph ga, LoopParams pa, DevGraph gb, LoopParams pb, const int64_t *work) {
+    k_teams(const DevGraph *__restrict__ views, const LoopParams *__restrict__ params, const int64_t *work) {
     __shared__ BfsStage s_stage;
     __shared__ Combine s_comb;
     if (threadIdx.x < 4) s_stage.cnt[threadIdx.x] = 0;
@@ -1622,11 +1817,13 @@ __global__ void __launch_bounds__(BLOCK)
     const int64_t wa = work[0], wb = work[1];
     int64_t sp = (wa + wb) > 0 ? ((int64_t)G * wa + (wa + wb) / 2) / (wa + wb) : G / 2;
     const int split = (int)min((int64_t)G - 1, max((int64_t)1, sp));
-    if ((int)blockIdx.x < split)
-        solve_loop<kAgent>(ga, Team{(int)blockIdx.x, split}, pa, &s_stage, pa.combine ? &s_comb : nullptr);
-    else
-        solve_loop<kAgent>(gb, Team{(int)blockIdx.x - split, G - split}, pb, &s_stage,
-                           pb.combine ? &s_comb : nullptr);
+    // one inlined loop; the view and its parameters are read by reference from
+    // the device table (a private copy of either would be indexed dynamically
+    // and spill)
+    const int side = (int)blockIdx.x < split ? 0 : 1;
+    const Team tm = side == 0 ? Team{(int)blockIdx.x, split} : Team{(int)blockIdx.x - split, G - split};
+    const LoopParams &p = params[side];
+    solve_loop<kAgent, WALK>(views[side], tm, p, &s_stage, p.combine ? &s_comb : nullptr);
 }
 
 // ---------------------------------------------------------------------------
@@ -1976,7 +2173,7 @@ __global__ void __launch_bounds__(BLOCK)
     LoopParams q = p;
     q.kc = kc[i];
     if (q.relabel_budget <= 0) q.relabel_budget = max((int64_t)1024, (int64_t)g.n / 16);
-    solve_loop<kGroup>(g, tm, q, nullptr, nullptr);
+    solve_loop<kGroup, false>(g, tm, q, nullptr, nullptr);
     __syncthreads();
     if (threadIdx.x == 0) {
         BatchResult r;
@@ -2038,10 +2235,14 @@ hipError_t launch_clamp(const DevGraph &g, const int64_t *ids, int64_t k, hipStr
 }
 
 hipError_t loop_max_coresident(int device, int *blocks) {
-    int per_cu = 0, cus = 0;
+    int per_cu = 0, per_cu2 = 0, cus = 0;
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &per_cu, reinterpret_cast<const void *>(k_loop<kBlock, kAgent>), kBlock, 0);
+        &per_cu, reinterpret_cast<const void *>(k_loop<kBlock, kAgent, true>), kBlock, 0);
     if (e != hipSuccess) return e;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &per_cu2, reinterpret_cast<const void *>(k_loop<kBlock, kAgent, false>), kBlock, 0);
+    if (e != hipSuccess) return e;
+    per_cu = min(per_cu, per_cu2);
     e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
     if (e != hipSuccess) return e;
     *blocks = per_cu * cus;
@@ -2050,14 +2251,16 @@ hipError_t loop_max_coresident(int device, int *blocks) {
 
 hipError_t launch_loop(const DevGraph &g, const LoopParams &p, int grid, hipStream_t st) {
     if (grid <= 1) {
-        hipLaunchKernelGGL((k_loop<kBlock, kGroup>), dim3(1), dim3(kBlock), 0, st, g, p);
+        if (p.walk) hipLaunchKernelGGL((k_loop<kBlock, kGroup, true>), dim3(1), dim3(kBlock), 0, st, g, p);
+        else hipLaunchKernelGGL((k_loop<kBlock, kGroup, false>), dim3(1), dim3(kBlock), 0, st, g, p);
         return hipGetLastError();
     }
     DevGraph ga = g;
     LoopParams pa = p;
     void *args[] = {&ga, &pa};
-    return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_loop<kBlock, kAgent>), dim3(grid),
-                                      dim3(kBlock), args, 0, st);
+    const void *fn = p.walk ? reinterpret_cast<const void *>(k_loop<kBlock, kAgent, true>)
+                            : reinterpret_cast<const void *>(k_loop<kBlock, kAgent, false>);
+    return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(kBlock), args, 0, st);
 }
 
 hipError_t launch_batch(const DevGraph *graphs, const int32_t *order, int count, const LoopParams &p,
@@ -2079,22 +2282,27 @@ hipError_t launch_batch(const DevGraph *graphs, const int32_t *order, int count,
     return hipGetLastError();
 }
 
-hipError_t launch_teams(const DevGraph &ga, const LoopParams &pa, const DevGraph &gb, const LoopParams &pb,
-                        const int64_t *work, int grid, hipStream_t st) {
+hipError_t launch_teams(const DevGraph *d_views, const LoopParams *d_params, bool walk, const int64_t *work,
+                        int grid, hipStream_t st) {
     if (grid < 2) return hipErrorInvalidValue;
-    DevGraph a = ga, b = gb;
-    LoopParams x = pa, y = pb;
+    const DevGraph *v = d_views;
+    const LoopParams *q = d_params;
     const int64_t *w = work;
-    void *args[] = {&a, &x, &b, &y, &w};
-    return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_teams<kBlock>), dim3(grid), dim3(kBlock),
-                                      args, 0, st);
+    void *args[] = {&v, &q, &w};
+    const void *fn = walk ? reinterpret_cast<const void *>(k_teams<kBlock, true>)
+                          : reinterpret_cast<const void *>(k_teams<kBlock, false>);
+    return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(kBlock), args, 0, st);
 }
 
 hipError_t teams_max_coresident(int device, int *blocks) {
-    int per_cu = 0, cus = 0;
+    int per_cu = 0, per_cu2 = 0, cus = 0;
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &per_cu, reinterpret_cast<const void *>(k_teams<kBlock>), kBlock, 0);
+        &per_cu, reinterpret_cast<const void *>(k_teams<kBlock, true>), kBlock, 0);
     if (e != hipSuccess) return e;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &per_cu2, reinterpret_cast<const void *>(k_teams<kBlock, false>), kBlock, 0);
+    if (e != hipSuccess) return e;
+    per_cu = min(per_cu, per_cu2);
     e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
     if (e != hipSuccess) return e;
     *blocks = per_cu * cus;

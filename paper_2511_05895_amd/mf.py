@@ -17,6 +17,7 @@ MF_MODE_DATA, MF_MODE_TOPOLOGY = 0, 1
 MF_FLAG_GAP = 1
 MF_FLAG_PUSH_PULL = 2
 MF_FLAG_DEBUG_CHECKS = 4
+MF_FLAG_SCAN_FIRST = 8
 _NAMES = {1: "MF_EINVAL", 2: "MF_ENOMEM", 3: "MF_EDEVICE", 4: "MF_ESTATE", 5: "MF_ETIMEOUT",
           6: "MF_EPENDING", 7: "MF_EBUSY"}
 
