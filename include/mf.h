@@ -234,6 +234,22 @@ MF_API int mf_apply_updates(mf_handle_t *h, const int64_t *edge_ids, const int32
 MF_API int mf_apply_updates_device(mf_handle_t *h, const int64_t *d_edge_ids,
                                    const int32_t *d_new_caps, int64_t k);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): as
+ * mf_apply_updates (host arrays, same rules and errors), but the batch is
+ * staged in a static device array of this GPU instead of buffers the handle
+ * allocates, and the call allocates nothing (no hipMalloc, hipFree or pinned
+ * host memory).  At most MF_NOALLOC_MAX_UPDATES updates per call (12 MiB of
+ * staging per GPU, held until the process ends); a larger k returns
+ * MF_EINVAL and leaves the handle unchanged.  Every handle on one GPU shares
+ * that GPU's array: calls that overlap on one GPU (from several threads) race
+ * and must be serialised by the caller.  With MF_FLAG_PUSH_PULL the second
+ * view of the state is allocated by mf_create, so that path allocates
+ * nothing either. */
+#define MF_NOALLOC_MAX_UPDATES 1048576
+MF_API int mf_apply_updates_noalloc(mf_handle_t *h, const int64_t *edge_ids, const int32_t *new_caps,
+                                    int64_t k);
+
 /* Change capacities without repairing or solving (host arrays, same rules
  * as mf_apply_updates).  Leaves the handle unsolved: mf_solve must run before
  * queries.  This is how the static comparator sees an updated graph. */

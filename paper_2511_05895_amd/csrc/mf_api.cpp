@@ -685,6 +685,9 @@ MF_API int mf_create(const mf_csr_t *g, const int32_t *cap, int32_t s, int32_t t
     };
     hipError_t e = hipSetDevice(o.device);
     if (e != hipSuccess) return bail(MF_EDEVICE, std::string("hipSetDevice: ") + hipGetErrorString(e));
+    // device address of this GPU's staging array for mf_apply_updates_noalloc
+    if ((e = mf::noalloc_scratch_setup(o.device)) != hipSuccess)
+        return bail(MF_EDEVICE, std::string("hipGetSymbolAddress: ") + hipGetErrorString(e));
     if ((e = hipStreamCreateWithFlags(&h->own_stream, hipStreamNonBlocking)) != hipSuccess)
         return bail(MF_EDEVICE, std::string("hipStreamCreate: ") + hipGetErrorString(e));
     h->stream = h->own_stream;
@@ -886,6 +889,29 @@ MF_API int mf_apply_updates_device(mf_handle_t *h, const int64_t *d_edge_ids, co
     if (!h) return fail(nullptr, MF_EINVAL, "null handle");
     HIP_TRY(h, hipSetDevice(h->device));
     return apply_device(h, d_edge_ids, d_new_caps, k);
+}
+
+MF_API int mf_apply_updates_noalloc(mf_handle_t *h, const int64_t *edge_ids, const int32_t *new_caps, int64_t k) {
+    static_assert(MF_NOALLOC_MAX_UPDATES == mf::kNoAllocMaxUpdates, "staging size");
+    if (!h) return fail(nullptr, MF_EINVAL, "null handle");
+    if (k < 0 || k > h->g.m) return fail(h, MF_EINVAL, "batch size k must be in [0, m]");
+    if (k > mf::kNoAllocMaxUpdates)
+        return fail(h, MF_EINVAL, "mf_apply_updates_noalloc takes at most " +
+                                      std::to_string(mf::kNoAllocMaxUpdates) + " updates per call");
+    if (k > 0 && (!edge_ids || !new_caps)) return fail(h, MF_EINVAL, "null batch arrays");
+    HIP_TRY(h, hipSetDevice(h->device));
+    uint8_t *base = static_cast<uint8_t *>(mf::noalloc_scratch(h->device));
+    if (!base) return fail(h, MF_ESTATE, "the device's staging array was not set up");
+    int64_t *d_ids = reinterpret_cast<int64_t *>(base);
+    int32_t *d_caps = reinterpret_cast<int32_t *>(base + mf::kNoAllocIdsBytes);
+    if (k > 0) {
+        HIP_TRY(h, hipMemcpyAsync(d_ids, edge_ids, sizeof(int64_t) * k, hipMemcpyHostToDevice, h->stream));
+        HIP_TRY(h, hipMemcpyAsync(d_caps, new_caps, sizeof(int32_t) * k, hipMemcpyHostToDevice, h->stream));
+    }
+    const int rc = apply_device(h, d_ids, d_caps, k);
+    // the caller's arrays and the staging are free again once this returns
+    if (rc) (void)hipStreamSynchronize(h->stream);
+    return rc;
 }
 
 MF_API int mf_set_capacities(mf_handle_t *h, const int64_t *edge_ids, const int32_t *new_caps, int64_t k) {

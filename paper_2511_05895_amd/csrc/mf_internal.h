@@ -266,6 +266,16 @@ hipError_t launch_view_merge(const DevGraph &g, const int2 *varc, const int64_t 
 // Per-edge flow (int32[m]) of the valid flow whose residuals are carc[].y.
 hipError_t launch_edge_flow(const DevGraph &g, const int2 *carc, int32_t *rem, int32_t *flow, hipStream_t st);
 
+// Batch staging of mf_apply_updates_noalloc: a static device array per GPU
+// (int64 ids, then int32 capacities) for at most kNoAllocMaxUpdates updates.
+constexpr int64_t kNoAllocMaxUpdates = 1 << 20;
+constexpr int64_t kNoAllocIdsBytes = kNoAllocMaxUpdates * (int64_t)sizeof(int64_t);
+constexpr int64_t kNoAllocCapsBytes = kNoAllocMaxUpdates * (int64_t)sizeof(int32_t);
+// Resolve the array's device address on `device` (once per device; call with
+// the handle's set-up).  noalloc_scratch returns it, or null before set-up.
+hipError_t noalloc_scratch_setup(int device);
+void *noalloc_scratch(int device);
+
 // True once the process has begun to exit (the C atexit handlers run).  The
 // HIP runtime tears itself down in those handlers, so objects released after
 // that point free only their host memory; the device memory goes with the

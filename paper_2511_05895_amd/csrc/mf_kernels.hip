@@ -31,6 +31,8 @@
 //    repaired by RemoveInvalidEdges).
 #include "mf_internal.h"
 
+#include <mutex>
+
 namespace mf {
 
 // ---------------------------------------------------------------------------
@@ -2355,5 +2357,42 @@ hipError_t launch_fill_i32(int32_t *p, int64_t count, int32_t value, hipStream_t
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Batch staging of the allocation-free update call: one array per GPU, held
+// until the process ends.  Host code never hands the array's name to a
+// kernel (in host code it is only a stand-in for the symbol); its device
+// address comes from hipGetSymbolAddress, once per device with that device
+// current, and the kernels take that address like any other batch pointer.
+// ---------------------------------------------------------------------------
+
+static __device__ __align__(256) uint8_t scratch[kNoAllocIdsBytes + kNoAllocCapsBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t noalloc_scratch_setup(int device) {
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[device]) return hipSuccess;
+    int cur = 0;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != device && (e = hipSetDevice(device)) != hipSuccess) return e;
+    void *ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (cur != device) (void)hipSetDevice(cur);
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[device] = ptr;
+    return hipSuccess;
+}
+
+void *noalloc_scratch(int device) {
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return g_scratch_ptr[device];
+}
 
 }  // namespace mf

@@ -18,6 +18,7 @@ MF_FLAG_GAP = 1
 MF_FLAG_PUSH_PULL = 2
 MF_FLAG_DEBUG_CHECKS = 4
 MF_FLAG_SCAN_FIRST = 8
+MF_NOALLOC_MAX_UPDATES = 1 << 20  # batch limit of mf_apply_updates_noalloc
 _NAMES = {1: "MF_EINVAL", 2: "MF_ENOMEM", 3: "MF_EDEVICE", 4: "MF_ESTATE", 5: "MF_ETIMEOUT",
           6: "MF_EPENDING", 7: "MF_EBUSY"}
 
@@ -100,6 +101,7 @@ _SIGS = {
     "mf_solve": (C.c_int, [C.c_void_p]),
     "mf_apply_updates": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64]),
     "mf_apply_updates_device": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64]),
+    "mf_apply_updates_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64]),
     "mf_set_capacities": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64]),
     "mf_resume": (C.c_int, [C.c_void_p]),
     "mf_flow_value": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
@@ -236,6 +238,14 @@ def mf_apply_updates(h, edge_ids, new_caps):
     if ids.shape != caps.shape:
         raise ValueError("edge_ids and new_caps differ in length")
     return _check(lib().mf_apply_updates(h, _ptr(ids), _ptr(caps), ids.shape[0]), h)
+
+
+def mf_apply_updates_noalloc(h, edge_ids, new_caps):
+    ids = np.ascontiguousarray(edge_ids, dtype=np.int64)
+    caps = np.ascontiguousarray(new_caps, dtype=np.int32)
+    if ids.shape != caps.shape:
+        raise ValueError("edge_ids and new_caps differ in length")
+    return _check(lib().mf_apply_updates_noalloc(h, _ptr(ids), _ptr(caps), ids.shape[0]), h)
 
 
 def mf_apply_updates_device(h, d_edge_ids_ptr: int, d_new_caps_ptr: int, k: int):
@@ -423,6 +433,10 @@ class MaxFlow:
 
     def update(self, edge_ids, new_caps) -> int:
         mf_apply_updates(self.h, edge_ids, new_caps)
+        return mf_flow_value(self.h)
+
+    def update_noalloc(self, edge_ids, new_caps) -> int:
+        mf_apply_updates_noalloc(self.h, edge_ids, new_caps)
         return mf_flow_value(self.h)
 
     def update_device(self, ids_tensor, caps_tensor) -> int:
