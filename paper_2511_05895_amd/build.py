@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(os.path.dirname(HERE), "_build", "mf")
 LIB = os.path.join(HERE, "libmf.so")
-SOURCES = ["mf_kernels.hip", "mf_policy.hip", "mf_api.cpp", "mf_policy_api.cpp", "mf_batch.cpp", "mf_server.cpp", "build_pairs.cpp"]
+SOURCES = ["mf_kernels.hip", "mf_build.hip", "mf_policy.hip", "mf_api.cpp", "mf_policy_api.cpp", "mf_batch.cpp", "mf_server.cpp", "build_pairs.cpp"]
 ARCH = os.environ.get("MF_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

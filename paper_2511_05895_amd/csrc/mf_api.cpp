@@ -70,6 +70,9 @@ struct mf_handle {
     int32_t lazy_items = 0;
     int32_t bu_alpha = 0;  // direction rule of the BFS (0: top-down only)
     int32_t walk = 1;      // long arc lists visited by the downhill walk (else scan first)
+    int32_t local_stage = 1;  // dynamic updates run the local stage before the global loop
+    int32_t *d_pmark = nullptr;  // n: list tags of the local pulls
+    int32_t ptag = 0;            // last tag used
     int32_t combine = 0;
     double tick_ms = 1e-5;  // one wall-clock tick in ms
     int32_t seq = 1;  // next round id; round ids stamp mark[] and rmark[]
@@ -120,6 +123,9 @@ constexpr int32_t kLazyItems = 1024;
 // arcs not reached yet; back to top-down below n / beta frontier vertices.
 constexpr int32_t kBuAlpha = 14;
 constexpr int32_t kBuBeta = 24;
+// Rounds of local pulls into the deficits a batch leaves (the last one
+// without handing deficits on).
+constexpr int kPullRounds = 4;
 
 int fail(mf_handle_t *h, int code, const std::string &msg) {
     if (h) h->err = msg;
@@ -585,6 +591,16 @@ int apply_device(mf_handle_t *h, const int64_t *d_ids, const int32_t *d_caps, in
         rc = push_pull(h);
     } else {
         HIP_TRY(h, mf::launch_saturate_source(h->g, h->stream));
+        // the local stage reads the cut of the last global relabel: only from
+        // a solved state
+        if (h->local_stage && h->state == State::Solved && k > 0) {
+            if (h->ptag > INT32_MAX - 2 * (kPullRounds + 1)) {
+                HIP_TRY(h, mf::launch_fill_i32(h->d_pmark, h->g.n, 0, h->stream));
+                h->ptag = 0;
+            }
+            HIP_TRY(h, mf::launch_local_stage(h->g, d_ids, k, h->d_pmark, h->ptag + 1, kPullRounds, h->stream));
+            h->ptag += kPullRounds + 1;
+        }
         rc = run_loop_and_finish(h);
     }
     if (rc == MF_EINVAL) return update_error_text(h, h->h_ctrl->err);
@@ -599,7 +615,7 @@ bool opts_valid(const mf_opts_t &o, std::string *why) {
     if (o.time_budget_ms < 0) { *why = "time_budget_ms must be >= 0"; return false; }
     if (o.max_rounds < 0) { *why = "max_rounds must be >= 0"; return false; }
     if (o.relabel_budget < 0) { *why = "relabel_budget must be >= 0"; return false; }
-    if (o.flags & ~(MF_FLAG_GAP | MF_FLAG_PUSH_PULL | MF_FLAG_DEBUG_CHECKS | MF_FLAG_SCAN_FIRST)) {
+    if (o.flags & ~(MF_FLAG_GAP | MF_FLAG_PUSH_PULL | MF_FLAG_DEBUG_CHECKS | MF_FLAG_SCAN_FIRST | MF_FLAG_GLOBAL_ONLY)) {
         *why = "unknown flags";
         return false;
     }
@@ -640,20 +656,15 @@ MF_API int mf_create(const mf_csr_t *g, const int32_t *cap, int32_t s, int32_t t
     mf_default_opts(&o);
     if (opts) o = *opts;
     if (!opts_valid(o, &why)) return fail(nullptr, MF_EINVAL, why);
-    mf::HostPairs hp;
-    try {
-        if (mf::build_pairs(n, m, g->row_ptr, g->col, cap, &hp, &why))
-            return fail(nullptr, MF_EINVAL, why);
-    } catch (const std::bad_alloc &) {
-        return fail(nullptr, MF_ENOMEM, "host allocation failed while building arc pairs");
+    // the per-edge capacity limit falls with the edges merged into one pair:
+    // a capacity above the limit of an unshared pair is refused at once (the
+    // exact limit is checked after the build)
+    {
+        const int64_t lim1 = mf::edge_cap_limit(1);
+        for (int64_t i = 0; i < m; ++i)
+            if (cap[i] > lim1)
+                return fail(nullptr, MF_EINVAL, "capacity above the per-edge limit " + std::to_string(lim1));
     }
-    // per-edge capacity limit: after the deltas of one batch land, an arc's
-    // residual is at most twice the pair's capacity sum, which must fit int32
-    const int64_t lim = mf::edge_cap_limit(hp.max_pair_mult);
-    for (int64_t i = 0; i < m; ++i)
-        if (cap[i] > lim)
-            return fail(nullptr, MF_EINVAL,
-                        "capacity above the per-edge limit " + std::to_string(lim));
 
     mf_handle_t *h = new (std::nothrow) mf_handle_t();
     if (!h) return fail(nullptr, MF_ENOMEM, "host allocation failed");
@@ -662,7 +673,6 @@ MF_API int mf_create(const mf_csr_t *g, const int32_t *cap, int32_t s, int32_t t
     h->free_fn = o.dev_free;
     h->alloc_ctx = o.alloc_ctx;
     h->debug_checks = (o.flags & MF_FLAG_DEBUG_CHECKS) ? 1 : 0;
-    h->cap_limit = (int32_t)lim;
     h->mode = o.mode;
     h->max_iter = o.max_iterations;
     const int64_t budget_ms = o.time_budget_ms > 0 ? o.time_budget_ms : 60000;
@@ -672,6 +682,7 @@ MF_API int mf_create(const mf_csr_t *g, const int32_t *cap, int32_t s, int32_t t
     h->use_gap = (o.flags & MF_FLAG_GAP) ? 1 : 0;
     h->push_pull = (o.flags & MF_FLAG_PUSH_PULL) ? 1 : 0;
     h->walk = (o.flags & MF_FLAG_SCAN_FIRST) ? 0 : 1;
+    h->local_stage = (o.flags & MF_FLAG_GLOBAL_ONLY) ? 0 : 1;
     h->stall_rounds = o.stall_rounds == 0 ? 3 : (o.stall_rounds < 0 ? 0 : o.stall_rounds);
     h->solo_items = o.solo_items == 0 ? kSoloItems : (o.solo_items < 0 ? 0 : o.solo_items);
     h->lazy_items = o.lazy_items == 0 ? kLazyItems : (o.lazy_items < 0 ? INT32_MAX : o.lazy_items);
@@ -697,11 +708,49 @@ MF_API int mf_create(const mf_csr_t *g, const int32_t *cap, int32_t s, int32_t t
     if ((e = hipHostMalloc((void **)&h->h_ctrl, sizeof(mf::Ctrl), hipHostMallocDefault)) != hipSuccess)
         return bail(MF_ENOMEM, "pinned control block");
 
+    // a0: the merged arc-pair layout, built on the device (mf_build.hip); the
+    // arc row pointers come back for the host-side lists below
+    mf::DevGraph &d = h->g;
+    std::vector<int32_t> hrow;
+    {
+        mf::BuildAlloc mem;
+        mem.alloc = [h](void **q, size_t bytes) { return raw_alloc(h, q, bytes); };
+        mem.release = [h](void *q) { raw_free(h, q); };
+        mem.alloc_keep = [h](void **q, size_t bytes) {
+            hipError_t e = raw_alloc(h, q, bytes);
+            if (e == hipSuccess) h->allocs.push_back(*q);
+            return e;
+        };
+        mf::DeviceLayout lay;
+        std::string berr;
+        try {
+            e = mf::build_layout_device(n, m, g->row_ptr, g->col, cap, mem, h->stream, &lay, &hrow, &berr);
+        } catch (const std::bad_alloc &) {
+            return bail(MF_ENOMEM, "host allocation failed while building arc pairs");
+        }
+        if (e == hipErrorInvalidValue) return bail(MF_EINVAL, berr);
+        if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
+            return bail(MF_ENOMEM, "device allocation failed while building arc pairs: " + berr);
+        if (e != hipSuccess) return bail(MF_EDEVICE, "arc-pair build: " + berr);
+        // per-edge capacity limit: after the deltas of one batch land, an arc's
+        // residual is at most twice the pair's capacity sum, which must fit int32
+        const int64_t lim = mf::edge_cap_limit(lay.max_pair_mult);
+        for (int64_t i = 0; i < m; ++i)
+            if (cap[i] > lim) return bail(MF_EINVAL, "capacity above the per-edge limit " + std::to_string(lim));
+        h->cap_limit = (int32_t)lim;
+        d.A = lay.A;
+        d.row_ptr = lay.row_ptr;
+        d.arc = lay.arc;
+        d.twin = lay.twin;
+        d.cap = lay.cap;
+        d.edge2arc = lay.edge2arc;
+        d.ecap = lay.ecap;
+    }
     // heavy vertices (arc lists handled by a wavefront in topology-driven sweeps)
     std::vector<int32_t> heavy;
     int64_t nhuge = 0;  // vertices visited by a whole workgroup
     for (int32_t v = 0; v < n; ++v) {
-        const int32_t deg = hp.row_ptr[v + 1] - hp.row_ptr[v];
+        const int32_t deg = hrow[v + 1] - hrow[v];
         if (v != s && v != t && deg > mf::kLightMaxDeg) heavy.push_back(v);
         if (v != s && v != t && deg > mf::kHugeDeg) nhuge++;
     }
@@ -710,26 +759,18 @@ MF_API int mf_create(const mf_csr_t *g, const int32_t *cap, int32_t s, int32_t t
     h->combine = nhuge > 0 ? 1 : 0;
     h->nhuge = nhuge;
 
-    mf::DevGraph &d = h->g;
     d.n = n;
     d.s = s;
     d.t = t;
-    d.A = hp.A;
     d.m = m;
-    d.qcap = (int64_t)n + hp.A / mf::kChunk + 64;
+    d.qcap = (int64_t)n + d.A / mf::kChunk + 64;
     d.n_heavy_all = (int32_t)heavy.size();
-    const int64_t A = hp.A;
+    const int64_t A = d.A;
 #define ALLOC(ptr, count)                                                             \
     do {                                                                              \
         if ((e = dev_alloc(h, &(ptr), (count))) != hipSuccess)                        \
             return bail(MF_ENOMEM, std::string("hipMalloc " #ptr ": ") + hipGetErrorString(e)); \
     } while (0)
-    ALLOC(d.row_ptr, (int64_t)n + 1);
-    ALLOC(d.arc, A);
-    ALLOC(d.twin, A);
-    ALLOC(d.cap, A);
-    ALLOC(d.edge2arc, m);
-    ALLOC(d.ecap, m);
     ALLOC(d.stamp, m);
     ALLOC(d.e, n);
     ALLOC(d.h, n);
@@ -748,24 +789,17 @@ MF_API int mf_create(const mf_csr_t *g, const int32_t *cap, int32_t s, int32_t t
     ALLOC(d.heavy_all, (int64_t)heavy.size());
     ALLOC(d.ctrl, 1);
     ALLOC(h->d_side, n);
+    ALLOC(h->d_pmark, n);
 #undef ALLOC
-    // upload: arc records {head, residual}; the residual is set by the solve
-    std::vector<int2> arc((size_t)A);
-    for (int64_t a = 0; a < A; ++a) arc[a] = make_int2(hp.col[a], hp.cap[a]);
     auto up = [&](void *dst, const void *src, size_t bytes) {
         return bytes ? hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, h->stream) : hipSuccess;
     };
-    if ((e = up(d.row_ptr, hp.row_ptr.data(), sizeof(int32_t) * (n + 1))) != hipSuccess ||
-        (e = up(d.arc, arc.data(), sizeof(int2) * A)) != hipSuccess ||
-        (e = up(d.twin, hp.twin.data(), sizeof(int32_t) * A)) != hipSuccess ||
-        (e = up(d.cap, hp.cap.data(), sizeof(int32_t) * A)) != hipSuccess ||
-        (e = up(d.edge2arc, hp.edge2arc.data(), sizeof(int32_t) * m)) != hipSuccess ||
-        (e = up(d.ecap, cap, sizeof(int32_t) * m)) != hipSuccess ||
-        (e = up(d.heavy_all, heavy.data(), sizeof(int32_t) * heavy.size())) != hipSuccess)
+    if ((e = up(d.heavy_all, heavy.data(), sizeof(int32_t) * heavy.size())) != hipSuccess)
         return bail(MF_EDEVICE, std::string("upload: ") + hipGetErrorString(e));
     if ((e = mf::launch_fill_i32(d.stamp, m, 0, h->stream)) != hipSuccess ||
         (e = mf::launch_fill_i32(d.mark, n, 0, h->stream)) != hipSuccess ||
         (e = mf::launch_fill_i32(d.rmark, n, 0, h->stream)) != hipSuccess ||
+        (e = mf::launch_fill_i32(h->d_pmark, n, 0, h->stream)) != hipSuccess ||
 
         (e = mf::launch_reset_ctrl(d, h->stream)) != hipSuccess ||
         (e = hipStreamSynchronize(h->stream)) != hipSuccess)
@@ -806,14 +840,14 @@ MF_API int mf_create(const mf_csr_t *g, const int32_t *cap, int32_t s, int32_t t
             items.reserve((size_t)n + (size_t)(A / mf::kChunk) + 1);
             std::vector<int32_t> longv;  // vertices with items left after the k-th
             for (int32_t v = 0; v < n; ++v) {
-                const int32_t b = hp.row_ptr[v], en = hp.row_ptr[v + 1];
+                const int32_t b = hrow[v], en = hrow[v + 1];
                 if (en > b) items.push_back(make_int4(v, b, std::min(en, b + mf::kChunk), 0));
                 if (en - b > mf::kChunk) longv.push_back(v);
             }
             for (int32_t k = 1; !longv.empty(); ++k) {
                 size_t keep = 0;
                 for (const int32_t v : longv) {
-                    const int32_t b = hp.row_ptr[v] + k * mf::kChunk, en = hp.row_ptr[v + 1];
+                    const int32_t b = hrow[v] + k * mf::kChunk, en = hrow[v + 1];
                     items.push_back(make_int4(v, b, std::min(en, b + mf::kChunk), 0));
                     if (en - b > mf::kChunk) longv[keep++] = v;
                 }

@@ -5,6 +5,10 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <functional>
+#include <string>
+#include <vector>
+
 namespace mf {
 
 // A vertex whose arc list is at most this long is handled by one lane in the
@@ -123,6 +127,7 @@ struct Ctrl {
     int32_t solo_r, solo_done, solo_reason, solo_last_change;
     int32_t check;      // failed invariants of the debug check (bits, see k_check_state)
     int32_t pad_;
+    int32_t pull_cnt[4];  // list sizes of the local pulls (ping-pong)
     int64_t stat[kStCount];
 };
 
@@ -223,6 +228,13 @@ hipError_t launch_validate_updates(const DevGraph &g, const int64_t *ids, const 
 hipError_t launch_apply_delta(const DevGraph &g, const int64_t *ids, const int32_t *caps, int64_t k,
                               hipStream_t st);
 hipError_t launch_clamp(const DevGraph &g, const int64_t *ids, int64_t k, hipStream_t st);
+// Local stage of a dynamic update (after the clamp and the source
+// re-saturation): saturate the updated arcs that cross the last cut from its
+// source side to its sink side, then `rounds` rounds of pulls into the
+// deficits at the batch's arc ends (the last round without handing deficits
+// on).  Uses list[1], list[2] and ctrl->pull_cnt; pmark tags tag0 .. tag0 + rounds.
+hipError_t launch_local_stage(const DevGraph &g, const int64_t *ids, int64_t k, int32_t *pmark, int32_t tag0,
+                              int rounds, hipStream_t st);
 hipError_t launch_loop(const DevGraph &g, const LoopParams &p, int grid, hipStream_t st);
 hipError_t launch_min_cut(const DevGraph &g, uint8_t *d_side, hipStream_t st);
 // Invariant check of the state into ctrl->check (cleared first): 1 c_f < 0,
@@ -275,6 +287,32 @@ constexpr int64_t kNoAllocCapsBytes = kNoAllocMaxUpdates * (int64_t)sizeof(int32
 // the handle's set-up).  noalloc_scratch returns it, or null before set-up.
 hipError_t noalloc_scratch_setup(int device);
 void *noalloc_scratch(int device);
+
+// Device build of the merged arc-pair layout (mf_build.hip).  alloc /
+// release: temporary device memory of the build; alloc_keep: memory the
+// handle keeps (and frees with itself).
+struct BuildAlloc {
+    std::function<hipError_t(void **, size_t)> alloc;
+    std::function<void(void *)> release;
+    std::function<hipError_t(void **, size_t)> alloc_keep;
+};
+struct DeviceLayout {
+    int32_t A = 0;
+    int32_t max_pair_mult = 1;  // most half-edges (input edges, either direction) in one arc pair
+    int32_t *row_ptr = nullptr;   // n+1
+    int2 *arc = nullptr;          // A: {head, capacity}
+    int32_t *twin = nullptr;      // A
+    int32_t *cap = nullptr;       // A
+    int32_t *edge2arc = nullptr;  // m, -1 for self-loops
+    int32_t *ecap = nullptr;      // m: the input capacities
+};
+// Inputs are host arrays already checked (row pointers monotone from 0 to m,
+// heads in range, capacities >= 0).  The arc row pointers come back to the
+// host in h_arc_row_ptr.  Errors: a HIP error, or hipErrorInvalidValue with *err
+// (too many arcs, a capacity sum above int32).
+hipError_t build_layout_device(int32_t n, int64_t m, const int64_t *h_row_ptr, const int32_t *h_col,
+                               const int32_t *h_cap, const BuildAlloc &mem, hipStream_t st, DeviceLayout *out,
+                               std::vector<int32_t> *h_arc_row_ptr, std::string *err);
 
 // True once the process has begun to exit (the C atexit handlers run).  The
 // HIP runtime tears itself down in those handlers, so objects released after

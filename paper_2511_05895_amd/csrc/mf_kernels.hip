@@ -2078,6 +2078,126 @@ __global__ void k_clamp(DevGraph g, const int64_t *ids, int64_t k) {
     if (lane_id() == 0 && cnt) add<kAgent>(&g.ctrl->stat[kStClamps], cnt);
 }
 
+// ---------------------------------------------------------------------------
+// Local stage of a dynamic update, between the batch repair (Alg. 5) and the
+// global loop: the updated arcs that now cross the last cut are saturated,
+// and the deficits the batch left are filled from excess nearby (the ideas of
+// Dynamic Push-Pull, Sec. 4.2 / Alg. 6 and 8, applied to the batch's own
+// arcs).  Every step is a push along a residual arc, so the global loop that
+// follows, with its unchanged termination test, still ends at a maximum flow;
+// the stage only saves it the work of letting every vertex that holds excess
+// on the source side chase a small deficit.
+// ---------------------------------------------------------------------------
+
+// Saturate every updated arc that is residual from the source side of the
+// last cut (height |V|) to its sink side (height < |V|).  A solved state has
+// no such arc, and only arcs whose capacity grew can have gained one: the
+// clamp and the source re-saturation only lower residuals across it.  The
+// flow moved becomes excess at the head and a deficit at the tail (Alg. 8,
+// "remove S to T edges", on the batch).  Heights are those of the last
+// global relabel.
+__global__ void k_cut_saturate(DevGraph g, const int64_t *ids, int64_t k) {
+    if (ld<kAgent>(&g.ctrl->err)) return;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < k;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t a0 = g.edge2arc[ids[i]];
+        if (a0 < 0) continue;
+        const int32_t a1 = g.twin[a0];
+        for (int side = 0; side < 2; ++side) {
+            const int32_t x = side ? a1 : a0, y = side ? a0 : a1;
+            const int head = g.arc[x].x, tail = g.arc[y].x;
+            if (g.h[tail] < g.n || g.h[head] >= g.n) continue;
+            if (ld<kAgent>(cf_ptr(g.arc, x)) <= 0) continue;
+            const int32_t c = xchg<kAgent>(cf_ptr(g.arc, x), 0);  // updates sharing the pair: one takes it
+            if (c > 0) {
+                add<kAgent>(cf_ptr(g.arc, y), c);
+                add<kAgent>(&g.e[tail], -(int64_t)c);
+                add<kAgent>(&g.e[head], (int64_t)c);
+            }
+        }
+    }
+}
+
+// The first list of the local pulls: the ends of the batch's arcs (other
+// than s and t) that hold a deficit, each once (pmark tag).
+__global__ void k_deficit_list(DevGraph g, const int64_t *ids, int64_t k, int32_t *pmark, int32_t tag,
+                               int32_t *list, int32_t *cnt) {
+    if (ld<kAgent>(&g.ctrl->err)) return;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < k;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t a0 = g.edge2arc[ids[i]];
+        if (a0 < 0) continue;
+        const int ends[2] = {g.arc[a0].x, g.arc[g.twin[a0]].x};
+        for (int j = 0; j < 2; ++j) {
+            const int v = ends[j];
+            if (v == g.s || v == g.t || ld<kAgent>(&g.e[v]) >= 0) continue;
+            if (xchg<kAgent>(&pmark[v], tag) == tag) continue;
+            list[fetch_add<kAgent>(cnt, 1)] = v;
+        }
+    }
+}
+
+// One round of local pulls.  Every deficient vertex v of list `in` takes what
+// it lacks from its in-neighbours w (residual arc w -> v) that hold excess,
+// in arc order: d moves as a push from w to v (c_f(w,v) -= d, c_f(v,w) += d,
+// e(w) -= d, e(v) += d), as Alg. 6 pulls, here without heights.  With `out`,
+// what is still lacking is then taken from in-neighbours along their residual
+// arcs whatever their excess, which hands the deficit on to them; a giver
+// left with a deficit joins `out` (once, pmark tag).  s and t never give.  A
+// wavefront per vertex; v's own excess is touched by its wavefront only.
+__global__ void k_pull_round(DevGraph g, const int32_t *in, const int32_t *in_cnt, int32_t *out, int32_t *out_cnt,
+                             int32_t *pmark, int32_t tag) {
+    if (ld<kAgent>(&g.ctrl->err)) return;
+    const int lane = lane_id();
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    const int cnt = ld<kAgent>(in_cnt);
+    for (int64_t i = wave; i < cnt; i += nwaves) {
+        const int v = in[i];
+        int64_t need = 0;
+        if (lane == 0) need = -ld<kAgent>(&g.e[v]);
+        need = __shfl(need, 0, 64);
+        if (need <= 0) continue;
+        const int beg = g.row_ptr[v], end = g.row_ptr[v + 1];
+        int64_t got = 0;
+        for (int hand_on = 0; hand_on < (out ? 2 : 1) && got < need; ++hand_on) {
+            for (int base = beg; base < end && got < need; base += 64) {
+                const int a = base + lane;
+                int64_t avail = 0;
+                int w = -1, tw = 0;
+                if (a < end) {
+                    w = g.arc[a].x;
+                    tw = g.twin[a];
+                    if (w != g.s && w != g.t) {
+                        const int32_t r = ld<kAgent>(cf_ptr(g.arc, tw));
+                        if (r > 0) {
+                            if (hand_on) {
+                                avail = r;
+                            } else {
+                                const int64_t ew = ld<kAgent>(&g.e[w]);
+                                if (ew > 0) avail = min((int64_t)r, ew);
+                            }
+                        }
+                    }
+                }
+                const int64_t incl = wave_incl_scan64(avail);
+                const int64_t excl = incl - avail;
+                const int64_t room = need - got;
+                const int64_t d = (avail > 0 && excl < room) ? min(avail, room - excl) : 0;
+                if (d > 0) {
+                    add<kAgent>(cf_ptr(g.arc, tw), -(int32_t)d);
+                    add<kAgent>(cf_ptr(g.arc, a), (int32_t)d);
+                    const int64_t old = fetch_add<kAgent>(&g.e[w], -d);
+                    if (out && old - d < 0 && xchg<kAgent>(&pmark[w], tag) != tag)
+                        out[fetch_add<kAgent>(out_cnt, 1)] = w;
+                }
+                got += min(__shfl(incl, 63, 64), room);
+            }
+        }
+        if (lane == 0 && got > 0) add<kAgent>(&g.e[v], got);
+    }
+}
+
 // Certificate: side[v] = 1 when h(v) >= |V|; cut = sum of cap over arcs from
 // the source side to the sink side (the tail of arc a is the head of twin(a)).
 __global__ void k_min_cut(DevGraph g, uint8_t *side) {
@@ -2342,6 +2462,27 @@ hipError_t launch_view_merge(const DevGraph &g, const int2 *varc, const int64_t 
 hipError_t launch_edge_flow(const DevGraph &g, const int2 *carc, int32_t *rem, int32_t *flow, hipStream_t st) {
     if (g.A > 0) hipLaunchKernelGGL(k_arc_flow, dim3(grid_for(g.A, 256)), dim3(256), 0, st, g, carc, rem);
     if (g.m > 0) hipLaunchKernelGGL(k_edge_flow, dim3(grid_for(g.m, 256)), dim3(256), 0, st, g, rem, flow);
+    return hipGetLastError();
+}
+
+hipError_t launch_local_stage(const DevGraph &g, const int64_t *ids, int64_t k, int32_t *pmark, int32_t tag0,
+                              int rounds, hipStream_t st) {
+    if (k <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_cut_saturate, dim3(grid_for(k, 256)), dim3(256), 0, st, g, ids, k);
+    int32_t *cnt = g.ctrl->pull_cnt;
+    int32_t *lists[2] = {g.list[1], g.list[2]};
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, cnt, (int64_t)4, 0);
+    hipLaunchKernelGGL(k_deficit_list, dim3(grid_for(k, 256)), dim3(256), 0, st, g, ids, k, pmark, tag0, lists[0],
+                       &cnt[0]);
+    // at most 2k deficits in the first list; a wavefront per deficit
+    const int blocks = grid_for(2 * k * 64, 256, 4096);
+    for (int r = 0; r < rounds; ++r) {
+        const bool last = r == rounds - 1;
+        int32_t *in = lists[r & 1], *out = last ? nullptr : lists[(r + 1) & 1];
+        hipLaunchKernelGGL(k_pull_round, dim3(blocks), dim3(256), 0, st, g, in, &cnt[r & 1], out,
+                           &cnt[(r + 1) & 1], pmark, tag0 + r + 1);
+        if (!last) hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, &cnt[r & 1], (int64_t)1, 0);
+    }
     return hipGetLastError();
 }
 

@@ -18,6 +18,7 @@ MF_FLAG_GAP = 1
 MF_FLAG_PUSH_PULL = 2
 MF_FLAG_DEBUG_CHECKS = 4
 MF_FLAG_SCAN_FIRST = 8
+MF_FLAG_GLOBAL_ONLY = 16
 MF_NOALLOC_MAX_UPDATES = 1 << 20  # batch limit of mf_apply_updates_noalloc
 _NAMES = {1: "MF_EINVAL", 2: "MF_ENOMEM", 3: "MF_EDEVICE", 4: "MF_ESTATE", 5: "MF_ETIMEOUT",
           6: "MF_EPENDING", 7: "MF_EBUSY"}

@@ -184,7 +184,9 @@ def test_torch_allocator_supplies_the_handle(mf):
     g = W.c1_random_1k()
     alloc = mf.TorchAllocator()
     with mf.MaxFlow(g, allocator=alloc, flags=mf.MF_FLAG_PUSH_PULL) as F:
-        assert alloc.calls > 20 and len(alloc.live) == alloc.calls
+        # the handle's arrays, and the arc-pair build's temporaries (returned
+        # before mf_create ends), all come from the allocator
+        assert alloc.calls > 20 and 20 < len(alloc.live) < alloc.calls
         F.solve()
         check_solved(F, g, g.cap)
         cap = g.cap.copy()

@@ -95,9 +95,12 @@ def test_init_state_matches_paper_init(mf):
 
 @pytest.mark.parametrize("seed", range(6))
 def test_update_repair_matches_paper_updates(mf, seed):
+    """The state after the batch repair (Alg. 5 with the re-saturation of
+    Alg. 4) equals the oracle's sequential repair bit for bit; the local stage
+    is off, since the oracle models the paper's repair alone."""
     g = W.random_graph(400, 3200, 1, 50, seed=100 + seed, s=0, t=399)
     rng = np.random.default_rng(seed)
-    with mf.MaxFlow(g) as F:
+    with mf.MaxFlow(g, flags=mf.MF_FLAG_GLOBAL_ONLY) as F:
         F.solve()
         cap = g.cap.copy()
         for j in range(3):
@@ -122,6 +125,30 @@ def test_update_repair_matches_paper_updates(mf, seed):
             F.set_max_iterations(-1)
             F.resume()
             check_solved(F, g, cap)
+
+
+@pytest.mark.parametrize("p_st", [0.0, 0.3])
+@pytest.mark.parametrize("which", ["c1", "grid", "rmat"])
+def test_local_stage_against_global_only(mf, which, p_st):
+    """Dynamic updates with the local stage (default) and without it
+    (MF_FLAG_GLOBAL_ONLY) reach the same value and canonical cut as the
+    oracle after every batch of a mixed chain, including batches biased to
+    the edges at s and t (which cross the cut)."""
+    if which == "c1":
+        g, inc, frac = W.c1_random_1k(), 100, 0.0125
+    elif which == "grid":
+        g, inc, frac = W.seg_grid(128, seed=61), 100, 0.01
+    else:
+        g, inc, frac = W.rmat(15, 16, seed=62), 1000, 0.002
+    with mf.MaxFlow(g) as L, mf.MaxFlow(g, flags=mf.MF_FLAG_GLOBAL_ONLY) as G:
+        assert L.solve() == G.solve()
+        cap = g.cap.copy()
+        for ids, new in W.batch_chain(g, frac, 5, inc, seed=W.SEED_BASE + 60, p_st=p_st):
+            cap[ids] = new
+            vl = L.update(ids, new)
+            assert vl == G.update(ids, new)
+            assert np.array_equal(L.min_cut()[0], G.min_cut()[0])
+            check_solved(L, g, cap)
 
 
 def test_clamp_with_parallel_and_antiparallel_edges(mf):

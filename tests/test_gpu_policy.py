@@ -92,7 +92,8 @@ def _features_now(P, batch_fraction):
 @pytest.mark.parametrize("grid", [1, 8])
 def test_phase0_features_match_oracle(mf, grid):
     g = W.c1_random_1k()
-    with mf.MaxFlow(g, grid_blocks=grid) as F:
+    # the oracle models the repair of Alg. 5 alone: no local stage
+    with mf.MaxFlow(g, grid_blocks=grid, flags=mf.MF_FLAG_GLOBAL_ONLY) as F:
         F.set_policy(None, mf.MF_POLICY_EXPLORE, explore=0.0)
         F.solve()
         tr = F.policy_trace()
