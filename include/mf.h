@@ -156,6 +156,16 @@ typedef struct {
  * default walk, which pushes downhill in arc order, stops once the excess is
  * gone and scans the whole list only to relabel.  Results are the same. */
 #define MF_FLAG_SCAN_FIRST 8
+/* opts.flags: dynamic updates go straight from the batch repair (Alg. 5) to
+ * the global loop of Alg. 4, without the default local stage.  The local
+ * stage, run from a solved state only, saturates the batch's arcs that now
+ * cross the last cut from its source side to its sink side (Alg. 8 on the
+ * batch) and then fills the deficits at the ends of the batch's arcs from
+ * in-neighbours that hold excess (pulls as in Alg. 6, without heights; a few
+ * rounds, handing what is still lacking on to the givers).  Every step is a
+ * push along a residual arc and the global loop's termination test is
+ * unchanged, so results are the same with or without it. */
+#define MF_FLAG_GLOBAL_ONLY 16
 
 /* Counters of the last mf_solve / mf_apply_updates* / mf_resume call. */
 typedef struct {
