@@ -720,7 +720,7 @@ def run_dynamic(config, args, K, Wm, cpu):
                           for leg, i in (("dynamic", 2), ("static", 3))},
         "exact": "dynamic value == static value on every step",
         "roofline": {
-            "kernel": "k_loop<1024, agent scope> (persistent solve loop)",
+            "kernel": "k_loop<1024, agent scope, walk> (persistent solve loop; dynamic and static launches)",
             "bound": "hbm",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
