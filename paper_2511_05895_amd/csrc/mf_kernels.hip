@@ -1364,35 +1364,39 @@ __device__ __forceinline__ void rie_arc(const DevGraph &g, int u, int hu, int a,
 template <int SC>
 __device__ void remove_invalid(const DevGraph &g, const Team &tm, const int32_t *list, int64_t count,
                                bool skip_cut, Tally &tl) {
-    const int64_t gtid = tm.tid();
-    const int64_t stride = tm.nthreads();
-    const int64_t cr = (count + 63) & ~63ll;
+    // a group of kLightGroup lanes per listed vertex: a short list is scanned by
+    // its group (arcs gl, gl + kLightGroup, ..., loads independent of each
+    // other); a long one by a whole wavefront after the group step
+    constexpr int G = 8;
+    const int64_t grp = tm.tid() / G, ngrp = tm.nthreads() / G;
+    const int gl = lane_id() & (G - 1);
     const int lane = lane_id();
-    for (int64_t i = gtid; i < cr; i += stride) {
-        int u = -1, beg = 0, end = 0;
+    const int64_t trips = (count + ngrp - 1) / ngrp;  // the same for every lane
+    for (int64_t k = 0, i = grp; k < trips; ++k, i += ngrp) {
+        int u = -1, beg = 0, end = 0, hu = 0;
         bool heavy = false;
         if (i < count) {
             u = list[i];
-            const int hu = g.h[u];
+            hu = g.h[u];
             if (skip_cut && hu >= g.n) {
                 u = -1;
             } else {
                 beg = g.row_ptr[u];
                 end = g.row_ptr[u + 1];
                 heavy = end - beg > kLightMaxDeg;
-                if (!heavy) {
-                    for (int a = beg; a < end; ++a) rie_arc<SC>(g, u, hu, a, tl);
-                    tl.rie_a += end - beg;
-                }
             }
         }
-        uint64_t hm = __ballot(heavy);
+        if (u >= 0 && !heavy) {
+            for (int a = beg + gl; a < end; a += G) rie_arc<SC>(g, u, hu, a, tl);
+            if (gl == 0) tl.rie_a += end - beg;
+        }
+        uint64_t hm = __ballot(heavy && gl == 0);
         while (hm) {
             const int l = __ffsll((unsigned long long)hm) - 1;
             hm &= hm - 1;
             const int w = __shfl(u, l, 64);
             const int wb = __shfl(beg, l, 64), we = __shfl(end, l, 64);
-            const int hw = g.h[w];
+            const int hw = __shfl(hu, l, 64);
             for (int a = wb + lane; a < we; a += 64) rie_arc<SC>(g, w, hw, a, tl);
             if (lane == 0) tl.rie_a += we - wb;
         }
