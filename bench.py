@@ -264,7 +264,7 @@ def run_serving(args):
     print(f"[bench] c5 graph generated in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
     nc, no = args.closed_requests, args.open_requests
     reqs = list(W.request_stream(g, nc + 2 * no, W.SEED_BASE + 4))
-    S = mf.Server(workers=args.workers)
+    S = mf.Server(workers=args.workers, max_group_requests=args.group_requests, max_group_edges=args.group_edges)
     t0 = time.perf_counter()
     gid, v0 = S.add_graph(g)
     print(f"[bench] admitted and solved in {time.perf_counter() - t0:.1f} s (value {v0})",
@@ -328,7 +328,8 @@ def run_serving(args):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "int32 capacities / int64 excess", "data": "synthetic (seeded generator)",
         "config": {"workload": CONFIGS["c5"]["desc"], "n": g.n, "m": g.m, "arcs": A,
-                   "workers": args.workers, "closed_requests": nc, "open_requests_per_load": no},
+                   "workers": args.workers, "closed_requests": nc, "open_requests_per_load": no,
+                   "max_group_requests": args.group_requests, "max_group_edges": args.group_edges},
         "closed_loop_service_ms": {"mean": float(svc.mean()), "p50": float(np.percentile(svc, 50)),
                                    "p99": float(np.percentile(svc, 99))},
         "load_0.5": phases[0.5], "load_0.8": hi,
@@ -564,6 +565,8 @@ def main():
     ap.add_argument("--p-st", type=float, default=0.0,
                     help="probability that a batch edge is drawn from the edges out of s / into t")
     ap.add_argument("--workers", type=int, default=2, help="serving workers (c5)")
+    ap.add_argument("--group-requests", type=int, default=64, help="requests one commit may merge (c5)")
+    ap.add_argument("--group-edges", type=int, default=1 << 20, help="edges one commit may merge (c5)")
     ap.add_argument("--closed-requests", type=int, default=30, help="closed-loop requests (c5)")
     ap.add_argument("--open-requests", type=int, default=100, help="open-loop requests per load (c5)")
     ap.add_argument("--train-calls", type=int, default=18, help="update calls per training graph (learned20)")

@@ -923,6 +923,11 @@ __device__ int discharge_walk(const DevGraph &g, int u, int kc, const RoundCtx &
                 }
             }
             walked += min(64, end - base);
+            if (__ballot(c > 0) == 0) {  // nothing downhill in this step (the common case
+                                         // of a walk that ends in a relabel)
+                if (v < 0 && hv != INT32_MAX) hrest = min(hrest, hv);
+                continue;
+            }
             const int64_t incl = wave_incl_scan64(c);
             const int64_t room = e0 - sent;
             const int64_t excl = incl - c;
@@ -1128,6 +1133,10 @@ __device__ int discharge_block_walk(const DevGraph &g, int u, int kc, const Roun
                 }
             }
             walked += min((int)blockDim.x, end - base);
+            if (!__syncthreads_or(c > 0)) {  // nothing downhill in this step of the workgroup
+                if (v < 0 && hv != INT32_MAX) hrest = min(hrest, hv);
+                continue;
+            }
             const int64_t incl = wave_incl_scan64(c);
             if (lane == 63) s_wsum[w] = incl;
             __syncthreads();
