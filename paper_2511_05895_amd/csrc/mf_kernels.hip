@@ -324,6 +324,12 @@ struct BfsStage {
     int32_t cnt[4];  // items, light, heavy, discovered vertices of this level
     int32_t res[6];  // the level's flush: global bases, then counts, of items, light, heavy
     int64_t arcs;    // arcs of the vertices this level discovered (direction rule)
+    // the direction rule's tallies of a level that is not staged (vertices
+    // and arcs discovered), added to the global counters once per workgroup:
+    // per wavefront step they would queue behind the frontier reservations
+    // on the same cache line
+    int32_t tverts;
+    int64_t tarcs;
 };
 
 // Reserve k slots of an LDS counter if they fit under cap (no partial
@@ -347,11 +353,12 @@ __device__ __forceinline__ int stage_reserve(int32_t *ctr, int k, int cap) {
 // by one lane, back to back so their round trips overlap, or in the
 // workgroup's stage (st).  counts: per-height vertex counts (gap heuristic);
 // feats: the schedule's features; track: vertices and arcs discovered per
-// level (the direction rule of the BFS).
+// level (the direction rule of the BFS), tallied in tst when the level is not
+// staged (null: straight to the global counters).
 template <int SC>
 __device__ __forceinline__ void bfs_emit(const DevGraph &g, int L, bool disc, int v, int vbeg, int vend, int64_t ev,
-                                         bool feats, bool counts, bool track, BfsStage *st, int2 *qout,
-                                         int32_t *qout_count, Tally &tl) {
+                                         bool feats, bool counts, bool track, BfsStage *st, BfsStage *tst,
+                                         int2 *qout, int32_t *qout_count, Tally &tl) {
     const int lane = lane_id();
     const int n = g.n;
     bool active = false;
@@ -385,7 +392,10 @@ __device__ __forceinline__ void bfs_emit(const DevGraph &g, int L, bool disc, in
         } else if (ndisc) {
             if (counts) add<SC>(&g.hcount[L + 1], ndisc);
             if (feats) add<SC>(&g.ctrl->feat_reached, ndisc);
-            if (track) {
+            if (track && tst) {
+                atomicAdd(&tst->tverts, ndisc);
+                atomicAdd(reinterpret_cast<unsigned long long *>(&tst->tarcs), (unsigned long long)darcs);
+            } else if (track) {
                 add<SC>(&g.ctrl->qverts[(L + 1) % 3], ndisc);
                 add<SC>(&g.ctrl->qarcs[(L + 1) % 3], darcs);
             }
@@ -450,6 +460,20 @@ __device__ void bfs_flush(const DevGraph &g, int L, BfsStage *st, bool counts, b
     for (int i = threadIdx.x; i < nh; i += blockDim.x) g.list[0][n - 1 - (st->res[2] + i)] = st->heavy[i];
 }
 
+// End of a level that was not staged: the workgroup's direction tallies go to
+// the global counters, one atomic each (every thread of the workgroup calls
+// it; the next use of the tallies comes after a barrier).
+template <int SC>
+__device__ void bfs_tally_flush(const DevGraph &g, int L, BfsStage *tst) {
+    __syncthreads();
+    if (threadIdx.x == 0 && tst->tverts) {
+        add<SC>(&g.ctrl->qverts[(L + 1) % 3], tst->tverts);
+        add<SC>(&g.ctrl->qarcs[(L + 1) % 3], tst->tarcs);
+        tst->tverts = 0;
+        tst->tarcs = 0;
+    }
+}
+
 // One BFS level, top-down: for every arc (w -> v) of a frontier item, v joins
 // level L+1 when it is unvisited (height |V|), is not s, and has residual
 // capacity toward w (the twin arc v -> w).  Newly reached vertices become
@@ -461,7 +485,7 @@ __device__ void bfs_flush(const DevGraph &g, int L, BfsStage *st, bool counts, b
 // it.
 template <int SC>
 __device__ void bfs_level(const DevGraph &g, const Team &tm, int L, int cnt, bool feats, bool counts,
-                          bool track, bool lazy, BfsStage *st, Tally &tl) {
+                          bool track, bool lazy, BfsStage *st, BfsStage *tst, Tally &tl) {
     const int2 *__restrict__ qin = g.q[L & 1];
     int2 *qout = g.q[(L + 1) & 1];
     int32_t *qout_count = &g.ctrl->qcount[(L + 1) % 3];
@@ -522,10 +546,14 @@ __device__ void bfs_level(const DevGraph &g, const Team &tm, int L, int cnt, boo
                     disc = cas<SC>(&g.h[v], n, L + 1);
                 }
             }
-            bfs_emit<SC>(g, L, disc, v, vbeg, vend, ev, feats, counts, track, st, qout, qout_count, tl);
+            bfs_emit<SC>(g, L, disc, v, vbeg, vend, ev, feats, counts, track, st, st ? nullptr : tst, qout,
+                         qout_count, tl);
         }
     }
-    if (st) bfs_flush<SC>(g, L, st, counts, feats, track, qout, qout_count);
+    if (st)
+        bfs_flush<SC>(g, L, st, counts, feats, track, qout, qout_count);
+    else if (track && tst)
+        bfs_tally_flush<SC>(g, L, tst);
 }
 
 // One BFS level, bottom-up (the direction-optimising BFS): every vertex v
@@ -602,7 +630,7 @@ __device__ void bfs_bottom_up(const DevGraph &g, const Team &tm, int L, bool fea
             vend = g.row_ptr[v + 1];
             ev = g.e[v];
         }
-        bfs_emit<SC>(g, L, disc, v, vbeg, vend, ev, feats, counts, true, st, qout, qout_count, tl);
+        bfs_emit<SC>(g, L, disc, v, vbeg, vend, ev, feats, counts, true, st, nullptr, qout, qout_count, tl);
     }
     if (st) bfs_flush<SC>(g, L, st, counts, feats, true, qout, qout_count);
 }
@@ -1527,6 +1555,10 @@ __device__ void solve_loop(const DevGraph &g, const Team &tm, const LoopParams &
     // vertices per height are counted only for the gap heuristic
     const bool counts = p.use_gap != 0;
     const uint64_t t0 = wall_clock64();
+    // arcs of the vertices that the previous global relabel of this launch
+    // reached (-1: none yet); the BFS direction rule takes the other arcs as
+    // those a bottom-up level scans in full without finding a parent
+    int64_t reach_prev = -1;
     for (;;) {
         // time budget: the leader raised `stop` before the last barrier, so
         // every workgroup sees the same value here
@@ -1553,9 +1585,12 @@ __device__ void solve_loop(const DevGraph &g, const Team &tm, const LoopParams &
         // them: every phase, or the first phase of a call decided per call
         const bool feats = policy && !(p.policy_per_call && iter > 0);
         // direction rule of the BFS (direction-optimising BFS): a level runs
-        // bottom-up when its frontier's arcs are a large share of the arcs of
-        // the vertices not reached yet, and stays so while the frontier is
-        // large; small and restricted BFS passes stay top-down
+        // bottom-up when its frontier's arcs are a large share of the arcs
+        // that a bottom-up pass would scan, and stays so while the frontier is
+        // large; small and restricted BFS passes stay top-down.  A bottom-up
+        // pass stops early only at vertices it discovers: the vertices that
+        // no level will reach (estimated by those the previous global relabel
+        // did not reach) have their whole arc lists scanned at every level
         const bool dir = p.bu_alpha > 0 && g.bu_items != nullptr && !g.part_restrict;
         bfs_roots<SC>(g, tm, counts, feats, dir, tl);
         if (!grid_barrier(c, tm, bar_epoch, p.barrier_ticks)) return;
@@ -1563,13 +1598,17 @@ __device__ void solve_loop(const DevGraph &g, const Team &tm, const LoopParams &
         bool bu = false;
         int64_t seen_arcs = 0;  // arcs of the vertices reached so far
         for (;;) {
+            // the level's counters are loaded together: one round trip after
+            // the barrier, not one per counter
             const int cnt = uniform(ld<SC>(&c->qcount[L % 3]));
+            const int64_t fa = dir ? uniform(ld<SC>(&c->qarcs[L % 3])) : 0;
+            const int fv = dir ? uniform(ld<SC>(&c->qverts[L % 3])) : 0;
             if (cnt == 0) break;
             if (dir) {
-                const int64_t fa = uniform(ld<SC>(&c->qarcs[L % 3]));
-                const int fv = uniform(ld<SC>(&c->qverts[L % 3]));
                 seen_arcs += fa;
-                bu = bu ? (int64_t)fv * p.bu_beta >= g.n : fa * p.bu_alpha > (int64_t)g.A - seen_arcs;
+                const int64_t rest = (int64_t)g.A - seen_arcs;
+                const int64_t dead = reach_prev < 0 ? 0 : min(rest, max((int64_t)0, (int64_t)g.A - reach_prev));
+                bu = bu ? (int64_t)fv * p.bu_beta >= g.n : fa * p.bu_alpha > rest + (p.bu_alpha - 1) * dead;
             }
             // A small frontier is expanded by the first workgroup alone, level
             // after level with workgroup barriers in between (no grid barrier,
@@ -1590,7 +1629,7 @@ __device__ void solve_loop(const DevGraph &g, const Team &tm, const LoopParams &
                         bfs_bottom_up<SC>(g, bt, L, feats, counts, stage, tl);
                     else
                         bfs_level<SC>(g, bt, L, k, feats, counts, dir, k >= p.lazy_items,
-                                      !alone && k >= kBfsStageMin ? stage : nullptr, tl);
+                                      !alone && k >= kBfsStageMin ? stage : nullptr, stage, tl);
                     if (!alone) break;
                     __syncthreads();
                     ++L;
@@ -1603,6 +1642,7 @@ __device__ void solve_loop(const DevGraph &g, const Team &tm, const LoopParams &
             if (!grid_barrier(c, tm, bar_epoch, p.barrier_ticks)) return;
             L = alone ? uniform(ld<SC>(&c->solo_level)) : L + 1;
         }
+        if (dir) reach_prev = seen_arcs;
         const uint64_t tp = wall_clock64();
         if (leader) {
             add<SC>(&c->stat[kStLevels], (int64_t)L);
@@ -1798,7 +1838,11 @@ __global__ void __launch_bounds__(BLOCK) k_loop(DevGraph g, LoopParams p) {
         __shared__ BfsStage s_stage;
         __shared__ Combine s_comb;
         if (threadIdx.x < 4) s_stage.cnt[threadIdx.x] = 0;
-        if (threadIdx.x == 0) s_stage.arcs = 0;
+        if (threadIdx.x == 0) {
+            s_stage.arcs = 0;
+            s_stage.tverts = 0;
+            s_stage.tarcs = 0;
+        }
         for (int i = threadIdx.x; i < kCombine; i += blockDim.x) {
             s_comb.key[i] = -1;
             s_comb.sum[i] = 0;
@@ -1822,7 +1866,11 @@ __global__ void __launch_bounds__(BLOCK)
     __shared__ BfsStage s_stage;
     __shared__ Combine s_comb;
     if (threadIdx.x < 4) s_stage.cnt[threadIdx.x] = 0;
-    if (threadIdx.x == 0) s_stage.arcs = 0;
+    if (threadIdx.x == 0) {
+        s_stage.arcs = 0;
+        s_stage.tverts = 0;
+        s_stage.tarcs = 0;
+    }
     for (int i = threadIdx.x; i < kCombine; i += blockDim.x) {
         s_comb.key[i] = -1;
         s_comb.sum[i] = 0;
