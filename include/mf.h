@@ -110,13 +110,21 @@ typedef struct {
                                yet looks for a parent on the frontier among
                                its own arcs and stops at the first) when the
                                frontier's arcs times this number exceed the
-                               arcs of the vertices not reached yet, and
-                               stays bottom-up while the frontier holds at
-                               least 1/24 of the vertices; the levels and
-                               heights are those of the top-down BFS;
-                               0 = 14, < 0 = top-down only (always so with
-                               one workgroup)                                */
-    int32_t reserved[1];    /* must be zero                                   */
+                               arcs of the vertices not reached yet, plus
+                               (this number - 1) times the arcs of those that
+                               the previous global relabel of the same call
+                               did not reach (a bottom-up level scans their
+                               lists in full), and stays bottom-up while the
+                               frontier holds at least 1/24 of the vertices;
+                               the levels and heights are those of the
+                               top-down BFS; 0 = 14, < 0 = top-down only
+                               (always so with one workgroup)                */
+    int32_t vertex_order;   /* MF_ORDER_*: how the handle numbers the vertices
+                               internally.  Falling degree puts the hubs'
+                               heights and excesses on a few cache lines and
+                               starts every arc list with its hub neighbours.
+                               Every call takes and returns the caller's
+                               vertex and edge ids whatever the order.        */
     /* Device memory of the handle (optional, both or neither): dev_alloc
      * returns `bytes` of device memory on opts.device (aligned to 256 bytes)
      * or NULL, dev_free releases it; both get alloc_ctx.  A caching allocator
@@ -150,6 +158,13 @@ typedef struct {
  * solved, no active vertex and no residual arc from the source side to the
  * sink side.  A failed check returns MF_EDEVICE naming it. */
 #define MF_FLAG_DEBUG_CHECKS 4
+/* opts.vertex_order: MF_ORDER_AUTO (0) numbers the vertices by falling
+ * degree (edges at either end, ties by id) for graphs of more than 8192
+ * vertices and keeps the caller's order for smaller ones; MF_ORDER_INPUT
+ * keeps the caller's order; MF_ORDER_DEGREE always numbers by degree. */
+#define MF_ORDER_AUTO 0
+#define MF_ORDER_INPUT 1
+#define MF_ORDER_DEGREE 2
 /* opts.flags: visit vertices of more than 32 arcs with the cycle of Alg. 2
  * as written (a scan of the whole arc list for the lowest residual neighbour
  * height, then pushes to the arcs at that height or a relabel) instead of the

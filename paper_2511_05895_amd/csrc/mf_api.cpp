@@ -73,6 +73,11 @@ struct mf_handle {
     int32_t local_stage = 1;  // dynamic updates run the local stage before the global loop
     int32_t *d_pmark = nullptr;  // n: list tags of the local pulls
     int32_t ptag = 0;            // last tag used
+    // Vertex numbering of the layout: the caller's vertex v is the handle's
+    // new_of_old[v] (both empty: the caller's numbering); caller_of_arc maps
+    // an arc of the layout to its index in the layout of the caller's
+    // numbering, computed on the first export or import that needs it.
+    std::vector<int32_t> new_of_old, old_of_new, caller_of_arc;
     int32_t combine = 0;
     double tick_ms = 1e-5;  // one wall-clock tick in ms
     int32_t seq = 1;  // next round id; round ids stamp mark[] and rmark[]
@@ -607,6 +612,29 @@ int apply_device(mf_handle_t *h, const int64_t *d_ids, const int32_t *d_caps, in
     return debug_check(h, rc);
 }
 
+// caller_of_arc of a renumbered handle, computed on the device on first use.
+int ensure_caller_order(mf_handle_t *h) {
+    if (h->new_of_old.empty() || (int64_t)h->caller_of_arc.size() == (int64_t)h->g.A) return MF_OK;
+    mf::BuildAlloc mem;
+    mem.alloc = [h](void **q, size_t bytes) { return raw_alloc(h, q, bytes); };
+    mem.release = [h](void *q) { raw_free(h, q); };
+    mem.alloc_keep = mem.alloc;
+    hipError_t e;
+    try {
+        e = mf::caller_arc_order(h->g.n, h->g.A, h->g.arc, h->g.twin, h->old_of_new, mem, h->stream,
+                                 &h->caller_of_arc);
+    } catch (const std::bad_alloc &) {
+        h->caller_of_arc.clear();
+        return fail(h, MF_ENOMEM, "host allocation failed while ordering the arcs");
+    }
+    if (e != hipSuccess) {
+        h->caller_of_arc.clear();
+        return fail(h, (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) ? MF_ENOMEM : MF_EDEVICE,
+                    std::string("arc order of the caller's numbering: ") + hipGetErrorString(e));
+    }
+    return MF_OK;
+}
+
 bool opts_valid(const mf_opts_t &o, std::string *why) {
     if (o.kernel_cycles < 0) { *why = "kernel_cycles must be >= 0"; return false; }
     if (o.mode != MF_MODE_DATA && o.mode != MF_MODE_TOPOLOGY) { *why = "unknown mode"; return false; }
@@ -620,7 +648,10 @@ bool opts_valid(const mf_opts_t &o, std::string *why) {
         return false;
     }
     if (!o.dev_alloc != !o.dev_free) { *why = "dev_alloc and dev_free go together"; return false; }
-    if (o.reserved[0]) { *why = "reserved fields must be zero"; return false; }
+    if (o.vertex_order < MF_ORDER_AUTO || o.vertex_order > MF_ORDER_DEGREE) {
+        *why = "unknown vertex_order";
+        return false;
+    }
     return true;
 }
 
@@ -723,8 +754,14 @@ MF_API int mf_create(const mf_csr_t *g, const int32_t *cap, int32_t s, int32_t t
         };
         mf::DeviceLayout lay;
         std::string berr;
+        const bool renumber = o.vertex_order == MF_ORDER_DEGREE || (o.vertex_order == MF_ORDER_AUTO && n > 8192);
         try {
-            e = mf::build_layout_device(n, m, g->row_ptr, g->col, cap, mem, h->stream, &lay, &hrow, &berr);
+            e = mf::build_layout_device(n, m, g->row_ptr, g->col, cap, renumber, mem, h->stream, &lay, &hrow,
+                                        &h->new_of_old, &berr);
+            if (e == hipSuccess && !h->new_of_old.empty()) {
+                h->old_of_new.assign((size_t)n, 0);
+                for (int32_t v = 0; v < n; ++v) h->old_of_new[h->new_of_old[v]] = v;
+            }
         } catch (const std::bad_alloc &) {
             return bail(MF_ENOMEM, "host allocation failed while building arc pairs");
         }
@@ -745,6 +782,11 @@ MF_API int mf_create(const mf_csr_t *g, const int32_t *cap, int32_t s, int32_t t
         d.cap = lay.cap;
         d.edge2arc = lay.edge2arc;
         d.ecap = lay.ecap;
+    }
+    // s and t in the layout's numbering
+    if (!h->new_of_old.empty()) {
+        s = h->new_of_old[s];
+        t = h->new_of_old[t];
     }
     // heavy vertices (arc lists handled by a wavefront in topology-driven sweeps)
     std::vector<int32_t> heavy;
@@ -1028,11 +1070,18 @@ MF_API int mf_min_cut(mf_handle_t *h, uint8_t *side_out, int64_t *cut_cap_out) {
     HIP_TRY(h, hipSetDevice(h->device));
     HIP_TRY(h, mf::launch_fill_i32(reinterpret_cast<int32_t *>(&h->g.ctrl->cut), 2, 0, h->stream));
     HIP_TRY(h, mf::launch_min_cut(h->g, h->d_side, h->stream));
-    if (side_out)
-        HIP_TRY(h, hipMemcpyAsync(side_out, h->d_side, (size_t)h->g.n, hipMemcpyDeviceToHost, h->stream));
+    const bool renum = !h->new_of_old.empty();
+    std::vector<uint8_t> side;
+    if (side_out) {
+        if (renum) side.resize((size_t)h->g.n);
+        HIP_TRY(h, hipMemcpyAsync(renum ? side.data() : side_out, h->d_side, (size_t)h->g.n, hipMemcpyDeviceToHost,
+                                  h->stream));
+    }
     int64_t cut = 0;
     HIP_TRY(h, hipMemcpyAsync(&cut, &h->g.ctrl->cut, sizeof(int64_t), hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(h, hipStreamSynchronize(h->stream));
+    if (side_out && renum)
+        for (int32_t v = 0; v < h->g.n; ++v) side_out[v] = side[h->new_of_old[v]];
     if (cut_cap_out) *cut_cap_out = cut;
     return MF_OK;
 }
@@ -1085,6 +1134,34 @@ MF_API int mf_export_graph(mf_handle_t *h, int32_t *row_ptr, int32_t *col, int32
     if (!h) return fail(nullptr, MF_EINVAL, "null handle");
     HIP_TRY(h, hipSetDevice(h->device));
     const mf::DevGraph &d = h->g;
+    if (!h->new_of_old.empty()) {
+        // the layout of the caller's numbering: arc a of the handle is arc
+        // pos[a] there, the caller's vertex v is the handle's nw[v]
+        const int rc = ensure_caller_order(h);
+        if (rc) return rc;
+        const std::vector<int32_t> &pos = h->caller_of_arc, &nw = h->new_of_old, &old = h->old_of_new;
+        std::vector<int32_t> rp((size_t)d.n + 1), tw((size_t)d.A), e2a((size_t)d.m);
+        std::vector<int2> arc((size_t)d.A);
+        HIP_TRY(h, hipMemcpyAsync(rp.data(), d.row_ptr, sizeof(int32_t) * (d.n + 1), hipMemcpyDeviceToHost, h->stream));
+        if (d.A) {
+            HIP_TRY(h, hipMemcpyAsync(arc.data(), d.arc, sizeof(int2) * d.A, hipMemcpyDeviceToHost, h->stream));
+            HIP_TRY(h, hipMemcpyAsync(tw.data(), d.twin, sizeof(int32_t) * d.A, hipMemcpyDeviceToHost, h->stream));
+        }
+        if (d.m)
+            HIP_TRY(h, hipMemcpyAsync(e2a.data(), d.edge2arc, sizeof(int32_t) * d.m, hipMemcpyDeviceToHost, h->stream));
+        HIP_TRY(h, hipStreamSynchronize(h->stream));
+        if (row_ptr) {
+            row_ptr[0] = 0;
+            for (int32_t v = 0; v < d.n; ++v) row_ptr[v + 1] = row_ptr[v] + (rp[nw[v] + 1] - rp[nw[v]]);
+        }
+        for (int64_t a = 0; a < d.A; ++a) {
+            if (col) col[pos[a]] = old[arc[a].x];
+            if (twin) twin[pos[a]] = pos[tw[a]];
+        }
+        if (edge2arc)
+            for (int64_t i = 0; i < d.m; ++i) edge2arc[i] = e2a[i] < 0 ? -1 : pos[e2a[i]];
+        return MF_OK;
+    }
     if (row_ptr)
         HIP_TRY(h, hipMemcpyAsync(row_ptr, d.row_ptr, sizeof(int32_t) * (d.n + 1), hipMemcpyDeviceToHost, h->stream));
     if (col && d.A) {
@@ -1105,6 +1182,34 @@ MF_API int mf_export_state(mf_handle_t *h, int32_t *cap, int32_t *cf, int64_t *e
     if (!h) return fail(nullptr, MF_EINVAL, "null handle");
     HIP_TRY(h, hipSetDevice(h->device));
     const mf::DevGraph &d = h->g;
+    if (!h->new_of_old.empty()) {
+        // per-arc and per-vertex arrays in the caller's numbering
+        const int rc = ensure_caller_order(h);
+        if (rc) return rc;
+        const std::vector<int32_t> &pos = h->caller_of_arc, &nw = h->new_of_old;
+        std::vector<int2> arc(cf ? (size_t)d.A : 0);
+        std::vector<int32_t> capi(cap ? (size_t)d.A : 0), hi(height ? (size_t)d.n : 0);
+        std::vector<int64_t> ei(e ? (size_t)d.n : 0);
+        if (cap && d.A)
+            HIP_TRY(h, hipMemcpyAsync(capi.data(), d.cap, sizeof(int32_t) * d.A, hipMemcpyDeviceToHost, h->stream));
+        if (cf && d.A)
+            HIP_TRY(h, hipMemcpyAsync(arc.data(), d.arc, sizeof(int2) * d.A, hipMemcpyDeviceToHost, h->stream));
+        if (e) HIP_TRY(h, hipMemcpyAsync(ei.data(), d.e, sizeof(int64_t) * d.n, hipMemcpyDeviceToHost, h->stream));
+        if (height)
+            HIP_TRY(h, hipMemcpyAsync(hi.data(), d.h, sizeof(int32_t) * d.n, hipMemcpyDeviceToHost, h->stream));
+        if (ecap && d.m)
+            HIP_TRY(h, hipMemcpyAsync(ecap, d.ecap, sizeof(int32_t) * d.m, hipMemcpyDeviceToHost, h->stream));
+        HIP_TRY(h, hipStreamSynchronize(h->stream));
+        for (int64_t a = 0; a < d.A; ++a) {
+            if (cap) cap[pos[a]] = capi[a];
+            if (cf) cf[pos[a]] = arc[a].y;
+        }
+        for (int32_t v = 0; v < d.n; ++v) {
+            if (e) e[v] = ei[nw[v]];
+            if (height) height[v] = hi[nw[v]];
+        }
+        return MF_OK;
+    }
     if (cap && d.A)
         HIP_TRY(h, hipMemcpyAsync(cap, d.cap, sizeof(int32_t) * d.A, hipMemcpyDeviceToHost, h->stream));
     if (cf && d.A) {
@@ -1128,6 +1233,25 @@ MF_API int mf_import_state(mf_handle_t *h, const int32_t *cap, const int32_t *cf
     HIP_TRY(h, hipSetDevice(h->device));
     HIP_TRY(h, hipStreamSynchronize(h->stream));
     const mf::DevGraph &d = h->g;
+    // a renumbered handle takes the caller's arrays into its own numbering
+    std::vector<int32_t> cap_in, cf_in;
+    std::vector<int64_t> e_in;
+    if (!h->new_of_old.empty()) {
+        const int rc = ensure_caller_order(h);
+        if (rc) return rc;
+        const std::vector<int32_t> &pos = h->caller_of_arc, &nw = h->new_of_old;
+        cap_in.resize((size_t)d.A);
+        cf_in.resize((size_t)d.A);
+        e_in.resize((size_t)d.n);
+        for (int64_t a = 0; a < d.A; ++a) {
+            cap_in[a] = cap[pos[a]];
+            cf_in[a] = cf[pos[a]];
+        }
+        for (int32_t v = 0; v < d.n; ++v) e_in[nw[v]] = e[v];
+        cap = cap_in.data();
+        cf = cf_in.data();
+        e = e_in.data();
+    }
     std::vector<int2> arc((size_t)d.A);
     std::vector<int32_t> twin((size_t)d.A), e2a((size_t)d.m), rp((size_t)d.n + 1);
     if (d.A) {

@@ -210,12 +210,17 @@ __global__ void k_nonloop(const int32_t *tail, const int32_t *col, int64_t m, in
 }
 
 // The two half-edges of every edge that is not a self-loop, at 2 * pos[i]:
-// key (owner << b) | neighbour, value (edge << 1) | reverse.
+// key (owner << b) | neighbour, value (edge << 1) | reverse.  With perm, the
+// ends are the vertices' numbers in the handle's order (perm[caller's id]).
 __global__ void k_half_edges(const int32_t *tail, const int32_t *col, int64_t m, const int64_t *pos, int b,
-                             uint64_t *keys, uint32_t *vals) {
+                             const int32_t *perm, uint64_t *keys, uint32_t *vals) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t u = tail[i], v = col[i];
+        int32_t u = tail[i], v = col[i];
         if (u == v) continue;
+        if (perm) {
+            u = perm[u];
+            v = perm[v];
+        }
         const int64_t p = 2 * pos[i];
         keys[p] = ((uint64_t)u << b) | (uint64_t)v;
         vals[p] = (uint32_t)((uint64_t)i << 1);
@@ -299,6 +304,45 @@ __global__ void k_twins(const int32_t *edge2arc, const int32_t *rev_arc, int64_t
     }
 }
 
+// Edges at every vertex (either end; self-loops left out).
+__global__ void k_degree(const int32_t *tail, const int32_t *col, int64_t m, int32_t *deg) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t u = tail[i], v = col[i];
+        if (u == v) continue;
+        atomicAdd(&deg[u], 1);
+        atomicAdd(&deg[v], 1);
+    }
+}
+
+// Sort keys of the vertices for falling degree, ties by id:
+// ((kDegMax - min(deg, kDegMax)) << b) | v.
+constexpr int kDegBits = 24;
+constexpr int32_t kDegMax = (1 << kDegBits) - 1;
+__global__ void k_vertex_keys(const int32_t *deg, int32_t n, int b, uint64_t *keys, uint32_t *vals) {
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t d = deg[v] < kDegMax ? deg[v] : kDegMax;
+        keys[v] = ((uint64_t)(kDegMax - d) << b) | (uint64_t)v;
+        vals[v] = (uint32_t)v;
+    }
+}
+
+// perm[v] = position of v in the sorted order.
+__global__ void k_rank_of(const uint32_t *sorted_vals, int64_t n, int32_t *perm) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        perm[sorted_vals[i]] = (int32_t)i;
+}
+
+// Key of every arc in the caller's numbering: (owner << b) | head, through
+// old_of_new (the tail of arc a is the head of its twin).
+__global__ void k_caller_arc_keys(const int2 *arc, const int32_t *twin, int64_t A, const int32_t *old_of_new, int b,
+                                  uint64_t *keys, uint32_t *vals) {
+    for (int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; a < A; a += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t u = (uint64_t)old_of_new[arc[twin[a]].x], v = (uint64_t)old_of_new[arc[a].x];
+        keys[a] = (u << b) | v;
+        vals[a] = (uint32_t)a;
+    }
+}
+
 __global__ void k_fill32(int32_t *p, int64_t count, int32_t value) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
         p[i] = value;
@@ -309,11 +353,41 @@ int grid_of(int64_t work) {
     return (int)(b < 1 ? 1 : (b > 16384 ? 16384 : b));
 }
 
+// Stable LSD sort of n (key, value) pairs on their low `bits` key bits, 4 bits
+// a pass, between the buffer pairs (k0, v0) and (k1, v1); the sorted pairs end
+// in (*k0, *v0) (the pointers are swapped as the passes go).  hist and scan:
+// kDigits * tiles and scan_tmp_count(kDigits * tiles) entries.
+hipError_t radix_sort(uint64_t **k0, uint32_t **v0, uint64_t **k1, uint32_t **v1, int64_t n, int bits,
+                      int64_t *hist, int64_t *scan, hipStream_t st) {
+    const int64_t tiles = (n + kSortTile - 1) / kSortTile;
+    if (n <= 1) return hipSuccess;
+    hipError_t e = hipMemsetAsync(hist, 0, sizeof(int64_t) * kDigits * tiles, st);
+    if (e != hipSuccess) return e;
+    for (int shift = 0; shift < bits; shift += 4) {
+        hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)tiles), dim3(kSortThreads), 0, st, *k0, n, shift, hist, tiles);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if ((e = scan_exclusive(hist, kDigits * tiles, scan, st)) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_rs_scatter, dim3((unsigned)tiles), dim3(kSortThreads), 0, st, *k0, *v0, n, shift, hist,
+                           tiles, *k1, *v1);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        std::swap(*k0, *k1);
+        std::swap(*v0, *v1);
+    }
+    return hipSuccess;
+}
+
+int id_bits(int64_t n) {
+    int b = 1;
+    while ((1ll << b) < n) ++b;
+    return b;
+}
+
 }  // namespace
 
 hipError_t build_layout_device(int32_t n, int64_t m, const int64_t *h_row_ptr, const int32_t *h_col,
-                               const int32_t *h_cap, const BuildAlloc &mem, hipStream_t st, DeviceLayout *out,
-                               std::vector<int32_t> *h_row_ptr_out, std::string *err) {
+                               const int32_t *h_cap, bool renumber, const BuildAlloc &mem, hipStream_t st,
+                               DeviceLayout *out, std::vector<int32_t> *h_row_ptr_out,
+                               std::vector<int32_t> *h_new_of_old, std::string *err) {
     std::vector<void *> tmp;
     auto talloc = [&](void **p, size_t bytes) -> hipError_t {
         hipError_t e = mem.alloc(p, bytes < 256 ? 256 : bytes);
@@ -371,39 +445,43 @@ hipError_t build_layout_device(int32_t n, int64_t m, const int64_t *h_row_ptr, c
         cleanup();
         return hipErrorInvalidValue;
     }
-    int b = 1;
-    while ((1ll << b) < n) ++b;  // bits of a vertex id
+    const int b = id_bits(n);  // bits of a vertex id
     uint64_t *d_k0 = nullptr, *d_k1 = nullptr;
     uint32_t *d_v0 = nullptr, *d_v1 = nullptr;
-    const int64_t nhh = nh > 0 ? nh : 1;
+    const int64_t nhh = std::max<int64_t>(nh > 0 ? nh : 1, renumber ? n : 1);
     BTRY(talloc((void **)&d_k0, sizeof(uint64_t) * nhh));
     BTRY(talloc((void **)&d_k1, sizeof(uint64_t) * nhh));
     BTRY(talloc((void **)&d_v0, sizeof(uint32_t) * nhh));
     BTRY(talloc((void **)&d_v1, sizeof(uint32_t) * nhh));
+    const int64_t tiles = (nhh + kSortTile - 1) / kSortTile;
+    int64_t *d_scan2 = nullptr;
+    BTRY(talloc((void **)&d_hist, sizeof(int64_t) * kDigits * tiles));
+    BTRY(talloc((void **)&d_scan2, sizeof(int64_t) * scan_tmp_count(kDigits * tiles)));
+    // 2b: the handle's vertex order: falling degree (ties by id), so that the
+    // hubs' heights, excesses and row bounds share a few cache lines and
+    // every arc list starts with its hub neighbours
+    int32_t *d_perm = nullptr;
+    if (renumber && n > 0) {
+        BTRY(talloc((void **)&d_perm, sizeof(int32_t) * n));
+        BTRY(hipMemsetAsync(d_perm, 0, sizeof(int32_t) * n, st));
+        if (m > 0) hipLaunchKernelGGL(k_degree, dim3(grid_of(m)), dim3(256), 0, st, d_tail, d_col, m, d_perm);
+        hipLaunchKernelGGL(k_vertex_keys, dim3(grid_of(n)), dim3(256), 0, st, d_perm, n, b, d_k0, d_v0);
+        BTRY(hipGetLastError());
+        BTRY(radix_sort(&d_k0, &d_v0, &d_k1, &d_v1, n, b + kDegBits, d_hist, d_scan2, st));
+        hipLaunchKernelGGL(k_rank_of, dim3(grid_of(n)), dim3(256), 0, st, d_v0, (int64_t)n, d_perm);
+        BTRY(hipGetLastError());
+        h_new_of_old->assign((size_t)n, 0);
+        BTRY(hipMemcpyAsync(h_new_of_old->data(), d_perm, sizeof(int32_t) * n, hipMemcpyDeviceToHost, st));
+    } else {
+        h_new_of_old->clear();
+    }
     if (m > 0) {
-        hipLaunchKernelGGL(k_half_edges, dim3(grid_of(m)), dim3(256), 0, st, d_tail, d_col, m, d_flag, b, d_k0,
-                           d_v0);
+        hipLaunchKernelGGL(k_half_edges, dim3(grid_of(m)), dim3(256), 0, st, d_tail, d_col, m, d_flag, b, d_perm,
+                           d_k0, d_v0);
         BTRY(hipGetLastError());
     }
     // 3: sort by (owner, neighbour)
-    const int64_t tiles = (nh + kSortTile - 1) / kSortTile;
-    if (nh > 1) {
-        BTRY(talloc((void **)&d_hist, sizeof(int64_t) * kDigits * tiles));
-        BTRY(hipMemsetAsync(d_hist, 0, sizeof(int64_t) * kDigits * tiles, st));
-        int64_t *d_scan2 = nullptr;
-        BTRY(talloc((void **)&d_scan2, sizeof(int64_t) * scan_tmp_count(kDigits * tiles)));
-        for (int shift = 0; shift < 2 * b; shift += 4) {
-            hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)tiles), dim3(kSortThreads), 0, st, d_k0, nh, shift, d_hist,
-                               tiles);
-            BTRY(hipGetLastError());
-            BTRY(scan_exclusive(d_hist, kDigits * tiles, d_scan2, st));
-            hipLaunchKernelGGL(k_rs_scatter, dim3((unsigned)tiles), dim3(kSortThreads), 0, st, d_k0, d_v0, nh, shift,
-                               d_hist, tiles, d_k1, d_v1);
-            BTRY(hipGetLastError());
-            std::swap(d_k0, d_k1);
-            std::swap(d_v0, d_v1);
-        }
-    }
+    BTRY(radix_sort(&d_k0, &d_v0, &d_k1, &d_v1, nh, 2 * b, d_hist, d_scan2, st));
     // 4: arcs
     int64_t A = 0;
     int64_t *d_idx = nullptr;
@@ -466,6 +544,54 @@ hipError_t build_layout_device(int32_t n, int64_t m, const int64_t *h_row_ptr, c
     out->A = (int32_t)A;
     out->max_pair_mult = info[0] > 0 ? info[0] : 1;
     return hipSuccess;
+}
+
+hipError_t caller_arc_order(int32_t n, int64_t A, const int2 *arc, const int32_t *twin,
+                            const std::vector<int32_t> &old_of_new, const BuildAlloc &mem, hipStream_t st,
+                            std::vector<int32_t> *h_caller_of_arc) {
+    std::vector<void *> tmp;
+    auto talloc = [&](void **p, size_t bytes) -> hipError_t {
+        hipError_t e = mem.alloc(p, bytes < 256 ? 256 : bytes);
+        if (e == hipSuccess) tmp.push_back(*p);
+        return e;
+    };
+    hipError_t e = hipSuccess;
+    auto done = [&](hipError_t r) {
+        (void)hipStreamSynchronize(st);
+        for (void *p : tmp) mem.release(p);
+        return r;
+    };
+    const int64_t AA = A > 0 ? A : 1;
+    const int64_t tiles = (AA + kSortTile - 1) / kSortTile;
+    uint64_t *k0 = nullptr, *k1 = nullptr;
+    uint32_t *v0 = nullptr, *v1 = nullptr;
+    int32_t *d_old = nullptr, *d_rank = nullptr;
+    int64_t *hist = nullptr, *scan = nullptr;
+    if ((e = talloc((void **)&k0, sizeof(uint64_t) * AA)) != hipSuccess ||
+        (e = talloc((void **)&k1, sizeof(uint64_t) * AA)) != hipSuccess ||
+        (e = talloc((void **)&v0, sizeof(uint32_t) * AA)) != hipSuccess ||
+        (e = talloc((void **)&v1, sizeof(uint32_t) * AA)) != hipSuccess ||
+        (e = talloc((void **)&d_old, sizeof(int32_t) * (n > 0 ? n : 1))) != hipSuccess ||
+        (e = talloc((void **)&d_rank, sizeof(int32_t) * AA)) != hipSuccess ||
+        (e = talloc((void **)&hist, sizeof(int64_t) * kDigits * tiles)) != hipSuccess ||
+        (e = talloc((void **)&scan, sizeof(int64_t) * scan_tmp_count(kDigits * tiles))) != hipSuccess)
+        return done(e);
+    if (n > 0 && (e = hipMemcpyAsync(d_old, old_of_new.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, st)) !=
+                     hipSuccess)
+        return done(e);
+    const int b = id_bits(n);
+    if (A > 0) {
+        hipLaunchKernelGGL(k_caller_arc_keys, dim3(grid_of(A)), dim3(256), 0, st, arc, twin, A, d_old, b, k0, v0);
+        if ((e = hipGetLastError()) != hipSuccess) return done(e);
+        if ((e = radix_sort(&k0, &v0, &k1, &v1, A, 2 * b, hist, scan, st)) != hipSuccess) return done(e);
+        hipLaunchKernelGGL(k_rank_of, dim3(grid_of(A)), dim3(256), 0, st, v0, A, d_rank);
+        if ((e = hipGetLastError()) != hipSuccess) return done(e);
+    }
+    h_caller_of_arc->assign((size_t)A, 0);
+    if (A > 0 && (e = hipMemcpyAsync(h_caller_of_arc->data(), d_rank, sizeof(int32_t) * A, hipMemcpyDeviceToHost,
+                                     st)) != hipSuccess)
+        return done(e);
+    return done(hipSuccess);
 }
 
 }  // namespace mf

@@ -307,12 +307,26 @@ struct DeviceLayout {
     int32_t *ecap = nullptr;      // m: the input capacities
 };
 // Inputs are host arrays already checked (row pointers monotone from 0 to m,
-// heads in range, capacities >= 0).  The arc row pointers come back to the
-// host in h_arc_row_ptr.  Errors: a HIP error, or hipErrorInvalidValue with *err
+// heads in range, capacities >= 0).  With renumber, the layout numbers the
+// vertices by falling degree (edges at either end, ties by the caller's id):
+// vertex v of the caller is vertex (*h_new_of_old)[v] of the layout, and
+// edge ids (edge2arc) keep the caller's numbering; without it
+// *h_new_of_old comes back empty.  The arc row pointers come back to the host
+// in h_arc_row_ptr.  Errors: a HIP error, or hipErrorInvalidValue with *err
 // (too many arcs, a capacity sum above int32).
 hipError_t build_layout_device(int32_t n, int64_t m, const int64_t *h_row_ptr, const int32_t *h_col,
-                               const int32_t *h_cap, const BuildAlloc &mem, hipStream_t st, DeviceLayout *out,
-                               std::vector<int32_t> *h_arc_row_ptr, std::string *err);
+                               const int32_t *h_cap, bool renumber, const BuildAlloc &mem, hipStream_t st,
+                               DeviceLayout *out, std::vector<int32_t> *h_arc_row_ptr,
+                               std::vector<int32_t> *h_new_of_old, std::string *err);
+
+// Index of every arc of a renumbered layout in the layout the caller's
+// numbering gives (arcs sorted by the caller's (tail, head)), from the
+// device arrays arc and twin and the host array old_of_new (the inverse of
+// new_of_old); the result comes back to the host.  Temporary device memory
+// from mem: about 28 bytes per arc.
+hipError_t caller_arc_order(int32_t n, int64_t A, const int2 *arc, const int32_t *twin,
+                            const std::vector<int32_t> &old_of_new, const BuildAlloc &mem, hipStream_t st,
+                            std::vector<int32_t> *h_caller_of_arc);
 
 // True once the process has begun to exit (the C atexit handlers run).  The
 // HIP runtime tears itself down in those handlers, so objects released after

@@ -2206,6 +2206,12 @@ __global__ void k_deficit_list(DevGraph g, const int64_t *ids, int64_t k, int32_
 // arcs whatever their excess, which hands the deficit on to them; a giver
 // left with a deficit joins `out` (once, pmark tag).  s and t never give.  A
 // wavefront per vertex; v's own excess is touched by its wavefront only.
+// Each pass looks at no more than kPullScan arcs of v, the excess pass at the
+// front of v's list and the hand-on pass at its back, so that a hub costs a
+// bounded number of steps and the deficit is handed on to the neighbours at
+// the end of the list (the low-degree ones when vertices are numbered by
+// falling degree); what stays lacking is left to the global loop.
+constexpr int kPullScan = 4096;
 __global__ void k_pull_round(DevGraph g, const int32_t *in, const int32_t *in_cnt, int32_t *out, int32_t *out_cnt,
                              int32_t *pmark, int32_t tag) {
     if (ld<kAgent>(&g.ctrl->err)) return;
@@ -2222,11 +2228,13 @@ __global__ void k_pull_round(DevGraph g, const int32_t *in, const int32_t *in_cn
         const int beg = g.row_ptr[v], end = g.row_ptr[v + 1];
         int64_t got = 0;
         for (int hand_on = 0; hand_on < (out ? 2 : 1) && got < need; ++hand_on) {
-            for (int base = beg; base < end && got < need; base += 64) {
-                const int a = base + lane;
+            const int lo = hand_on ? max(beg, end - kPullScan) : beg;
+            const int hi = hand_on ? end : min(end, beg + kPullScan);
+            for (int step = 0; step < hi - lo && got < need; step += 64) {
+                const int a = hand_on ? hi - 64 - step + lane : lo + step + lane;
                 int64_t avail = 0;
                 int w = -1, tw = 0;
-                if (a < end) {
+                if (a >= lo && a < hi) {
                     w = g.arc[a].x;
                     tw = g.twin[a];
                     if (w != g.s && w != g.t) {

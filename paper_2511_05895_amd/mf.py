@@ -19,6 +19,7 @@ MF_FLAG_PUSH_PULL = 2
 MF_FLAG_DEBUG_CHECKS = 4
 MF_FLAG_SCAN_FIRST = 8
 MF_FLAG_GLOBAL_ONLY = 16
+MF_ORDER_AUTO, MF_ORDER_INPUT, MF_ORDER_DEGREE = 0, 1, 2
 MF_NOALLOC_MAX_UPDATES = 1 << 20  # batch limit of mf_apply_updates_noalloc
 _NAMES = {1: "MF_EINVAL", 2: "MF_ENOMEM", 3: "MF_EDEVICE", 4: "MF_ESTATE", 5: "MF_ETIMEOUT",
           6: "MF_EPENDING", 7: "MF_EBUSY"}
@@ -44,7 +45,7 @@ class mf_opts_t(C.Structure):
                 ("max_rounds", C.c_int32), ("relabel_budget", C.c_int32), ("rounds_per_level", C.c_int32),
                 ("flags", C.c_int32), ("stall_rounds", C.c_int32), ("solo_items", C.c_int32),
                 ("lazy_items", C.c_int32),
-                ("bottom_up", C.c_int32), ("reserved", C.c_int32 * 1), ("dev_alloc", ALLOC_FN), ("dev_free", FREE_FN),
+                ("bottom_up", C.c_int32), ("vertex_order", C.c_int32), ("dev_alloc", ALLOC_FN), ("dev_free", FREE_FN),
                 ("alloc_ctx", C.c_void_p)]
 
 
@@ -383,6 +384,7 @@ class MaxFlow:
     def __init__(self, g, kernel_cycles=0, mode=MF_MODE_DATA, grid_blocks=0, max_iterations=-1,
                  device=0, cap=None, time_budget_ms=0, max_rounds=0, relabel_budget=0,
                  rounds_per_level=0, flags=0, stall_rounds=0, solo_items=0, lazy_items=0, bottom_up=0,
+                 vertex_order=0,
                  allocator=None):
         """allocator: optional object with alloc(nbytes) -> device address (0
         on failure) and free(address); the handle's device memory then comes
@@ -397,6 +399,7 @@ class MaxFlow:
         o.solo_items = solo_items
         o.lazy_items = lazy_items
         o.bottom_up = bottom_up
+        o.vertex_order = vertex_order
         o.time_budget_ms = time_budget_ms
         o.max_rounds = max_rounds
         o.relabel_budget = relabel_budget

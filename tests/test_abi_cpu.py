@@ -52,7 +52,7 @@ def _create(n, rp, col, cap, s, t, opts=None):
     ("neg cap", "negative capacity"),
     ("row_ptr", "row_ptr"),
     ("mode", "unknown mode"),
-    ("reserved", "reserved"),
+    ("vertex order", "unknown vertex_order"),
     ("cap limit", "per-edge limit"),
     ("flags", "unknown flags"),
     ("alloc pair", "go together"),
@@ -76,9 +76,9 @@ def test_create_rejects_bad_arguments(case, expect):
     elif case == "mode":
         opts = mf.mf_default_opts()
         opts.mode = 7
-    elif case == "reserved":
+    elif case == "vertex order":
         opts = mf.mf_default_opts()
-        opts.reserved[0] = 1
+        opts.vertex_order = 3
     elif case == "cap limit":
         cap = [5, 1 << 30]
     elif case == "flags":
