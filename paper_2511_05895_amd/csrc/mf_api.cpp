@@ -48,11 +48,14 @@ struct mf_handle {
     mf::DevGraph g{};
     std::vector<void *> allocs;
     mf::Ctrl *h_ctrl = nullptr;  // pinned read-back of the control block
-    int64_t *d_ids = nullptr;    // staging for host update batches
+    // staging of host update batches: one device buffer and its pinned host
+    // copy, ids then capacities back to back, so that one copy uploads both;
+    // d_ids / d_caps point into it for the current call
+    void *d_stage = nullptr;
+    unsigned char *p_stage = nullptr;
+    int64_t staging_cap = 0;  // updates the buffers hold
+    int64_t *d_ids = nullptr;
     int32_t *d_caps = nullptr;
-    int64_t *p_ids = nullptr;    // pinned host copies they are uploaded from
-    int32_t *p_caps = nullptr;
-    int64_t staging_cap = 0;
     uint8_t *d_side = nullptr;
     int32_t cap_limit = 0;
     int32_t kc = 1;
@@ -180,10 +183,8 @@ void release(mf_handle_t *h) {
     if (h->stream) (void)hipStreamSynchronize(h->stream);
     for (void *p : h->allocs) raw_free(h, p);
     h->allocs.clear();
-    raw_free(h, h->d_ids);
-    raw_free(h, h->d_caps);
-    if (h->p_ids) (void)hipHostFree(h->p_ids);
-    if (h->p_caps) (void)hipHostFree(h->p_caps);
+    raw_free(h, h->d_stage);
+    if (h->p_stage) (void)hipHostFree(h->p_stage);
     raw_free(h, h->d_ptrace);
     if (h->h_ctrl) (void)hipHostFree(h->h_ctrl);
     if (h->h_vctrl) (void)hipHostFree(h->h_vctrl);
@@ -339,33 +340,31 @@ int next_epoch(mf_handle_t *h) {
 // pinned buffers are written or freed (a no-op after a completed call).
 int stage_host_batch(mf_handle_t *h, const int64_t *ids, const int32_t *caps, int64_t k) {
     HIP_TRY(h, hipStreamSynchronize(h->stream));
+    constexpr size_t kPer = sizeof(int64_t) + sizeof(int32_t);
     if (k > h->staging_cap) {
-        raw_free(h, h->d_ids);
-        raw_free(h, h->d_caps);
-        if (h->p_ids) (void)hipHostFree(h->p_ids);
-        if (h->p_caps) (void)hipHostFree(h->p_caps);
-        h->d_ids = nullptr;
-        h->d_caps = nullptr;
-        h->p_ids = nullptr;
-        h->p_caps = nullptr;
+        raw_free(h, h->d_stage);
+        if (h->p_stage) (void)hipHostFree(h->p_stage);
+        h->d_stage = nullptr;
+        h->p_stage = nullptr;
         h->staging_cap = 0;
-        int64_t want = std::max<int64_t>(k, 1024);
-        void *qi = nullptr, *qc = nullptr;
-        const bool got_i = raw_alloc(h, &qi, sizeof(int64_t) * want) == hipSuccess;
-        h->d_ids = static_cast<int64_t *>(qi);
-        const bool got_c = got_i && raw_alloc(h, &qc, sizeof(int32_t) * want) == hipSuccess;
-        h->d_caps = static_cast<int32_t *>(qc);
-        if (!got_i || !got_c ||
-            hipHostMalloc((void **)&h->p_ids, sizeof(int64_t) * want, hipHostMallocDefault) != hipSuccess ||
-            hipHostMalloc((void **)&h->p_caps, sizeof(int32_t) * want, hipHostMallocDefault) != hipSuccess)
+        const int64_t want = std::max<int64_t>(k, 1024);
+        if (raw_alloc(h, &h->d_stage, kPer * want) != hipSuccess) {
+            h->d_stage = nullptr;
             return fail(h, MF_ENOMEM, "cannot allocate the update staging buffers");
+        }
+        if (hipHostMalloc((void **)&h->p_stage, kPer * want, hipHostMallocDefault) != hipSuccess) {
+            h->p_stage = nullptr;
+            return fail(h, MF_ENOMEM, "cannot allocate the update staging buffers");
+        }
         h->staging_cap = want;
     }
+    // ids at [0, 8k), capacities at [8k, 12k) of both buffers
+    h->d_ids = static_cast<int64_t *>(h->d_stage);
+    h->d_caps = reinterpret_cast<int32_t *>(static_cast<unsigned char *>(h->d_stage) + sizeof(int64_t) * k);
     if (k > 0) {
-        std::memcpy(h->p_ids, ids, sizeof(int64_t) * k);
-        std::memcpy(h->p_caps, caps, sizeof(int32_t) * k);
-        HIP_TRY(h, hipMemcpyAsync(h->d_ids, h->p_ids, sizeof(int64_t) * k, hipMemcpyHostToDevice, h->stream));
-        HIP_TRY(h, hipMemcpyAsync(h->d_caps, h->p_caps, sizeof(int32_t) * k, hipMemcpyHostToDevice, h->stream));
+        std::memcpy(h->p_stage, ids, sizeof(int64_t) * k);
+        std::memcpy(h->p_stage + sizeof(int64_t) * k, caps, sizeof(int32_t) * k);
+        HIP_TRY(h, hipMemcpyAsync(h->d_stage, h->p_stage, kPer * k, hipMemcpyHostToDevice, h->stream));
     }
     return MF_OK;
 }

@@ -2179,25 +2179,6 @@ __global__ void k_cut_saturate(DevGraph g, const int64_t *ids, int64_t k) {
     }
 }
 
-// The first list of the local pulls: the ends of the batch's arcs (other
-// than s and t) that hold a deficit, each once (pmark tag).
-__global__ void k_deficit_list(DevGraph g, const int64_t *ids, int64_t k, int32_t *pmark, int32_t tag,
-                               int32_t *list, int32_t *cnt) {
-    if (ld<kAgent>(&g.ctrl->err)) return;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < k;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t a0 = g.edge2arc[ids[i]];
-        if (a0 < 0) continue;
-        const int ends[2] = {g.arc[a0].x, g.arc[g.twin[a0]].x};
-        for (int j = 0; j < 2; ++j) {
-            const int v = ends[j];
-            if (v == g.s || v == g.t || ld<kAgent>(&g.e[v]) >= 0) continue;
-            if (xchg<kAgent>(&pmark[v], tag) == tag) continue;
-            list[fetch_add<kAgent>(cnt, 1)] = v;
-        }
-    }
-}
-
 // One round of local pulls.  Every deficient vertex v of list `in` takes what
 // it lacks from its in-neighbours w (residual arc w -> v) that hold excess,
 // in arc order: d moves as a push from w to v (c_f(w,v) -= d, c_f(v,w) += d,
@@ -2207,31 +2188,63 @@ __global__ void k_deficit_list(DevGraph g, const int64_t *ids, int64_t k, int32_
 // left with a deficit joins `out` (once, pmark tag).  s and t never give.  A
 // wavefront per vertex; v's own excess is touched by its wavefront only.
 // Each pass looks at no more than kPullScan arcs of v, the excess pass at the
-// front of v's list and the hand-on pass at its back, so that a hub costs a
-// bounded number of steps and the deficit is handed on to the neighbours at
-// the end of the list (the low-degree ones when vertices are numbered by
-// falling degree); what stays lacking is left to the global loop.
+// front of v's list and the hand-on pass at its back (from the last chunk
+// backwards), so that a hub costs a bounded number of steps and the deficit
+// is handed on to the neighbours at the end of the list (the low-degree ones
+// when vertices are numbered by falling degree); what stays lacking is left
+// to the global loop.
 constexpr int kPullScan = 4096;
-__global__ void k_pull_round(DevGraph g, const int32_t *in, const int32_t *in_cnt, int32_t *out, int32_t *out_cnt,
-                             int32_t *pmark, int32_t tag) {
+// The first round takes its vertices from the batch itself (ids, k: both
+// ends of every updated arc pair, s and t left out, each deficient vertex
+// claimed once with tag - 1); the later ones from the list `in` of the round
+// before.  Marks only grow (pmark holds the largest tag given to a vertex,
+// tags rise from call to call), so a claim or an append takes a vertex only
+// if its mark is still below the tag: a vertex that round 0 already put on
+// the next round's list (tag) is not claimed again as a batch end (tag - 1)
+// while its first visit may still be running.  The list counters rotate over three words, cnt[r % 3] read and
+// cnt[(r + 1) % 3] appended to by round r, which clears cnt[(r + 2) % 3] for
+// round r + 1; they all start at zero with the call's control block.
+__global__ void k_pull_round(DevGraph g, const int64_t *ids, int64_t k, const int32_t *in, int32_t *cnt, int r,
+                             int32_t *out, int32_t *pmark, int32_t tag) {
     if (ld<kAgent>(&g.ctrl->err)) return;
     const int lane = lane_id();
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    const int cnt = ld<kAgent>(in_cnt);
-    for (int64_t i = wave; i < cnt; i += nwaves) {
-        const int v = in[i];
+    if (blockIdx.x == 0 && threadIdx.x == 0) cnt[(r + 2) % 3] = 0;
+    int32_t *out_cnt = &cnt[(r + 1) % 3];
+    const int64_t items = ids ? 2 * k : (int64_t)ld<kAgent>(&cnt[r % 3]);
+    for (int64_t i = wave; i < items; i += nwaves) {
+        int v = -1;
         int64_t need = 0;
-        if (lane == 0) need = -ld<kAgent>(&g.e[v]);
+        if (lane == 0) {
+            if (ids) {
+                const int32_t a0 = g.edge2arc[ids[i >> 1]];
+                const int w = a0 < 0 ? -1 : ((i & 1) ? g.arc[g.twin[a0]].x : g.arc[a0].x);
+                if (w >= 0 && w != g.s && w != g.t && ld<kAgent>(&g.e[w]) < 0 &&
+                    __hip_atomic_fetch_max(&pmark[w], tag - 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < tag - 1)
+                    v = w;
+            } else {
+                v = in[i];
+            }
+            if (v >= 0) need = -ld<kAgent>(&g.e[v]);
+        }
+        v = __shfl(v, 0, 64);
         need = __shfl(need, 0, 64);
         if (need <= 0) continue;
         const int beg = g.row_ptr[v], end = g.row_ptr[v + 1];
         int64_t got = 0;
+        // chunks of 64 arcs aligned to the start of v's list in both passes,
+        // so that an arc the first pass pushed along is read again by the
+        // same lane (its own earlier atomic orders the read; another lane's
+        // would not)
+        const int nchunks = (end - beg + 63) / 64;
         for (int hand_on = 0; hand_on < (out ? 2 : 1) && got < need; ++hand_on) {
             const int lo = hand_on ? max(beg, end - kPullScan) : beg;
             const int hi = hand_on ? end : min(end, beg + kPullScan);
-            for (int step = 0; step < hi - lo && got < need; step += 64) {
-                const int a = hand_on ? hi - 64 - step + lane : lo + step + lane;
+            const int c_first = hand_on ? nchunks - 1 : 0;
+            const int c_last = hand_on ? (lo - beg) / 64 : (hi - beg + 63) / 64 - 1;
+            for (int c = c_first; (hand_on ? c >= c_last : c <= c_last) && got < need; c += hand_on ? -1 : 1) {
+                const int a = beg + 64 * c + lane;
                 int64_t avail = 0;
                 int w = -1, tw = 0;
                 if (a >= lo && a < hi) {
@@ -2257,7 +2270,8 @@ __global__ void k_pull_round(DevGraph g, const int32_t *in, const int32_t *in_cn
                     add<kAgent>(cf_ptr(g.arc, tw), -(int32_t)d);
                     add<kAgent>(cf_ptr(g.arc, a), (int32_t)d);
                     const int64_t old = fetch_add<kAgent>(&g.e[w], -d);
-                    if (out && old - d < 0 && xchg<kAgent>(&pmark[w], tag) != tag)
+                    if (out && old - d < 0 &&
+                        __hip_atomic_fetch_max(&pmark[w], tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < tag)
                         out[fetch_add<kAgent>(out_cnt, 1)] = w;
                 }
                 got += min(__shfl(incl, 63, 64), room);
@@ -2538,19 +2552,16 @@ hipError_t launch_local_stage(const DevGraph &g, const int64_t *ids, int64_t k, 
                               int rounds, hipStream_t st) {
     if (k <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_cut_saturate, dim3(grid_for(k, 256)), dim3(256), 0, st, g, ids, k);
+    // the list counters (ctrl->pull_cnt) start at zero with the call's
+    // control block; at most 2k deficits in any list, a wavefront each
     int32_t *cnt = g.ctrl->pull_cnt;
     int32_t *lists[2] = {g.list[1], g.list[2]};
-    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, cnt, (int64_t)4, 0);
-    hipLaunchKernelGGL(k_deficit_list, dim3(grid_for(k, 256)), dim3(256), 0, st, g, ids, k, pmark, tag0, lists[0],
-                       &cnt[0]);
-    // at most 2k deficits in the first list; a wavefront per deficit
     const int blocks = grid_for(2 * k * 64, 256, 4096);
     for (int r = 0; r < rounds; ++r) {
         const bool last = r == rounds - 1;
-        int32_t *in = lists[r & 1], *out = last ? nullptr : lists[(r + 1) & 1];
-        hipLaunchKernelGGL(k_pull_round, dim3(blocks), dim3(256), 0, st, g, in, &cnt[r & 1], out,
-                           &cnt[(r + 1) & 1], pmark, tag0 + r + 1);
-        if (!last) hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, &cnt[r & 1], (int64_t)1, 0);
+        int32_t *out = last ? nullptr : lists[(r + 1) & 1];
+        hipLaunchKernelGGL(k_pull_round, dim3(blocks), dim3(256), 0, st, g, r == 0 ? ids : nullptr, k, lists[r & 1],
+                           cnt, r, out, pmark, tag0 + r + 1);
     }
     return hipGetLastError();
 }
