@@ -160,3 +160,29 @@ def test_default_order_by_size(mf):
         with mf.MaxFlow(g, vertex_order=mf.MF_ORDER_DEGREE) as F:
             F.solve()
             check_solved(F, g, g.cap)
+
+
+@pytest.mark.parametrize("order", [1, 2])
+def test_local_stage_batches_on_shared_ends(mf, order):
+    """Batches drawn from the edges of one inner hub and of s and t: many batch
+    ends are the same vertex, so the local pulls' claims contend (a vertex can
+    become a giver left in deficit while its own claim as a batch end is still
+    pending).  After every batch the value and cut equal the oracle's and the
+    exported state passes the validator (no negative residual, excesses and
+    deficits routable)."""
+    g = _hub_graph()
+    tails = g.tails()
+    hub = 4321
+    near = np.flatnonzero((tails == hub) | (g.col == hub) | (tails == g.s) | (g.col == g.t))
+    rng = np.random.default_rng(77 + order)
+    with mf.MaxFlow(g, vertex_order=order) as F:
+        F.solve()
+        cap = g.cap.copy()
+        for j in range(6):
+            k = int(rng.integers(200, 3000))
+            ids = np.sort(rng.choice(near, k, replace=False)).astype(np.int64)
+            up = rng.random(k) < 0.5
+            new = np.where(up, cap[ids] + rng.integers(1, 80, k), rng.integers(0, cap[ids] + 1)).astype(np.int32)
+            cap[ids] = new
+            F.update(ids, new)
+            check_solved(F, g, cap)
