@@ -74,6 +74,8 @@ enum : int {
     kStCount
 };
 
+// Groups of the two-level grid barrier.
+constexpr int kBarGroups = 8;
 struct alignas(128) PaddedU32 {
     uint32_t v;
     uint32_t pad[31];
@@ -95,8 +97,9 @@ struct alignas(32) ListCtr {
 // Device control block: barrier words on their own cache lines, then loop
 // counters.  Reset by k_reset_ctrl before every solving call.
 struct Ctrl {
-    PaddedU32 bar_count;  // monotonic barrier arrivals of the launch
+    PaddedU32 bar_count;  // monotonic barrier arrivals of the launch (groups, for large teams)
     PaddedU32 abort;
+    PaddedU32 bar_group[kBarGroups];  // arrivals per group of workgroups (two-level barrier)
     int32_t qcount[4];  // frontier items per BFS level, triple-buffered
     int32_t qverts[4];  // vertices discovered per BFS level (direction rule), same buffering
     int64_t qarcs[4];   // their arcs

@@ -172,9 +172,11 @@ struct Team {
     __device__ int64_t nwaves() const { return (int64_t)size * (blockDim.x >> 6); }
 };
 
-// Barrier of a team with a bounded wait.  Arrivals count up one monotonic
-// counter (cleared before every launch): barrier number `epoch` (0, 1, ...)
-// is complete once it reaches (epoch + 1) * size.  One release fence before
+// Barrier of a team with a bounded wait.  Arrivals count up monotonic
+// counters (cleared before every launch): barrier number `epoch` (0, 1, ...)
+// is complete once the top counter reaches (epoch + 1) * size, or, for a team
+// of 2 * kBarGroups workgroups or more, (epoch + 1) * kBarGroups, one count per
+// group whose own counter reached (epoch + 1) * its size.  One release fence before
 // the arrival and one acquire fence after the wait; the polls themselves are
 // relaxed loads, so waiting does not keep invalidating the caches that the
 // team's other workgroups are still working from.  Returns false when the
@@ -189,13 +191,33 @@ __device__ bool grid_barrier(Ctrl *c, const Team &tm, uint32_t &epoch, int64_t l
     }
     __shared__ int s_ok;
     __syncthreads();
-    const uint32_t target = (epoch + 1u) * (uint32_t)tm.size;
+    const uint32_t e1 = epoch + 1u;
     ++epoch;
     if (threadIdx.x == 0) {
         int ok = 1;
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        const uint32_t before =
-            __hip_atomic_fetch_add(&c->bar_count.v, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        // Arrivals: a team of 2 * kBarGroups workgroups or more arrives in
+        // kBarGroups groups (rank mod kBarGroups), each on a counter of its own
+        // line, and the last arrival of a group (the one that completes its
+        // count) acquires the group's writes and releases them on to the top
+        // counter, which every workgroup polls.  Arrivals on one word
+        // serialise; this way each word takes a group's share of them.
+        const int G = tm.size < 2 * kBarGroups ? 1 : kBarGroups;
+        uint32_t target, before;
+        if (G == 1) {
+            target = e1 * (uint32_t)tm.size;
+            before = __hip_atomic_fetch_add(&c->bar_count.v, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            const int gid = tm.rank % G;
+            const uint32_t ng = (uint32_t)((tm.size - gid + G - 1) / G);
+            target = e1 * (uint32_t)G;
+            before = target - 2u;  // not the last of its group: wait
+            if (__hip_atomic_fetch_add(&c->bar_group[gid].v, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1u ==
+                e1 * ng) {
+                __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+                before = __hip_atomic_fetch_add(&c->bar_count.v, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
         if ((int32_t)(before + 1u - target) < 0) {
             const uint64_t tw = wall_clock64();
             uint32_t spins = 0;
