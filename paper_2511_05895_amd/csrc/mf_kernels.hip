@@ -23,12 +23,14 @@
 //    counter or list that all workgroups share is updated once per workgroup
 //    and round (LDS sums and staging): atomics on one address serialise, and a
 //    round has thousands of wavefronts.
-//  * Memory ordering: residual capacities and excesses that other lanes may be
-//    changing are read with device-scope atomic loads before a push amount is
-//    fixed, so a push never exceeds the latest residual or excess (only the
-//    owner lowers c_f of its arcs and its own excess during a sweep).  Heights
-//    may be stale, which the method tolerates (Sec. 3: invalid edges are
-//    repaired by RemoveInvalidEdges).
+//  * Memory ordering: only the owner lowers c_f of its arcs and its own excess
+//    during a sweep; others only raise them.  The first cycle of a visit takes
+//    an arc's residual from the {head, residual} record it loads anyway (read
+//    after the round's barrier, so at most stale-low); later cycles of the
+//    same visit, and every excess, use device-scope atomic loads, so a push
+//    never exceeds the latest residual or excess.  Heights may be stale, which
+//    the method tolerates (Sec. 3: invalid edges are repaired by
+//    RemoveInvalidEdges).
 #include "mf_internal.h"
 
 #include <mutex>
@@ -882,7 +884,7 @@ __device__ int discharge_group(const DevGraph &g, int u, int kc, const RoundCtx 
                     const int2 r = g.arc[a];
                     tw = g.twin[a];
                     if (r.y > 0 && g.h[r.x] == hmin) {
-                        c = max(0, ld<SC>(cf_ptr(g.arc, a)));
+                        c = cyc == 0 ? r.y : max(0, ld<SC>(cf_ptr(g.arc, a)));
                         v = r.x;
                     }
                 }
@@ -967,7 +969,7 @@ __device__ int discharge_walk(const DevGraph &g, int u, int kc, const RoundCtx &
                 if (r.y > 0) {
                     hv = g.h[r.x];
                     if (hv < hu) {
-                        c = max(0, ld<SC>(cf_ptr(g.arc, a)));
+                        c = cyc == 0 ? r.y : max(0, ld<SC>(cf_ptr(g.arc, a)));
                         v = r.x;
                     }
                 }
@@ -1096,7 +1098,7 @@ __device__ int discharge_block(const DevGraph &g, int u, int kc, const RoundCtx 
                     const int2 r = g.arc[a];
                     tw = g.twin[a];
                     if (r.y > 0 && g.h[r.x] == hmin) {
-                        c = max(0, ld<SC>(cf_ptr(g.arc, a)));
+                        c = cyc == 0 ? r.y : max(0, ld<SC>(cf_ptr(g.arc, a)));
                         v = r.x;
                     }
                 }
@@ -1177,7 +1179,7 @@ __device__ int discharge_block_walk(const DevGraph &g, int u, int kc, const Roun
                 if (r.y > 0) {
                     hv = g.h[r.x];
                     if (hv < hu) {
-                        c = max(0, ld<SC>(cf_ptr(g.arc, a)));
+                        c = cyc == 0 ? r.y : max(0, ld<SC>(cf_ptr(g.arc, a)));
                         v = r.x;
                     }
                 }
