@@ -342,12 +342,16 @@ int stage_host_batch(mf_handle_t *h, const int64_t *ids, const int32_t *caps, in
     HIP_TRY(h, hipStreamSynchronize(h->stream));
     constexpr size_t kPer = sizeof(int64_t) + sizeof(int32_t);
     if (k > h->staging_cap) {
+        // geometric growth from a floor of min(m, 2^17) updates (1.5 MB): a
+        // stream of growing requests reallocates (device and pinned memory,
+        // both slow calls) a few times over the handle's life, not per request
+        const int64_t floor_k = std::min<int64_t>(std::max<int64_t>(h->g.m, 1), 1 << 17);
+        const int64_t want = std::max({k, 2 * h->staging_cap, floor_k});
         raw_free(h, h->d_stage);
         if (h->p_stage) (void)hipHostFree(h->p_stage);
         h->d_stage = nullptr;
         h->p_stage = nullptr;
         h->staging_cap = 0;
-        const int64_t want = std::max<int64_t>(k, 1024);
         if (raw_alloc(h, &h->d_stage, kPer * want) != hipSuccess) {
             h->d_stage = nullptr;
             return fail(h, MF_ENOMEM, "cannot allocate the update staging buffers");

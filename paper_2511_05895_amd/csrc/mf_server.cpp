@@ -317,7 +317,11 @@ MF_API int mf_server_add_graph(mf_server_t *s, const mf_csr_t *g, const int32_t 
     if (!s || !g || !graph_id) return sfail(MF_EINVAL, "null argument");
     const int64_t est = mf_estimate_device_bytes(g->n, g->m);
     if (est < 0) return sfail(MF_EINVAL, "negative graph size");
-    const int64_t need = est + 12 * std::min<int64_t>(g->m, s->opts.max_group_edges);
+    // the handle's batch staging: at least min(m, 2^17) updates (its floor), up
+    // to a commit's worth of edges, 12 bytes each plus the 64-byte header
+    const int64_t staged = std::max<int64_t>(std::min<int64_t>(g->m, s->opts.max_group_edges),
+                                             std::min<int64_t>(std::max<int64_t>(g->m, 1), 1 << 17));
+    const int64_t need = est + 12 * staged + 64;
     {
         std::lock_guard<std::mutex> lk(s->mu);
         if (s->reserved + need > s->budget)
