@@ -2290,15 +2290,30 @@ __global__ void k_pull_round(DevGraph g, const int64_t *ids, int64_t k, const in
                 const int64_t excl = incl - avail;
                 const int64_t room = need - got;
                 const int64_t d = (avail > 0 && excl < room) ? min(avail, room - excl) : 0;
+                int64_t moved = 0;
                 if (d > 0) {
-                    add<kAgent>(cf_ptr(g.arc, tw), -(int32_t)d);
-                    add<kAgent>(cf_ptr(g.arc, a), (int32_t)d);
+                    // The excess pass claims its share of w's excess first and
+                    // gives back what w no longer holds (other deficits may pull
+                    // from the same giver at once), so that it never overdraws a
+                    // giver: an overdrawn giver left after the last round is a
+                    // deficit that the global loop would reach from the whole
+                    // source side.  The hand-on pass takes along the residual
+                    // whatever w holds, and lists a giver it leaves in deficit.
                     const int64_t old = fetch_add<kAgent>(&g.e[w], -d);
-                    if (out && old - d < 0 &&
+                    moved = d;
+                    if (!hand_on) {
+                        moved = old >= d ? d : (old > 0 ? old : 0);
+                        if (moved < d) add<kAgent>(&g.e[w], d - moved);
+                    }
+                    if (moved > 0) {
+                        add<kAgent>(cf_ptr(g.arc, tw), -(int32_t)moved);
+                        add<kAgent>(cf_ptr(g.arc, a), (int32_t)moved);
+                    }
+                    if (out && hand_on && old - d < 0 &&
                         __hip_atomic_fetch_max(&pmark[w], tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < tag)
                         out[fetch_add<kAgent>(out_cnt, 1)] = w;
                 }
-                got += min(__shfl(incl, 63, 64), room);
+                got += wave_sum(moved);
             }
         }
         if (lane == 0 && got > 0) add<kAgent>(&g.e[v], got);
