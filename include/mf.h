@@ -248,9 +248,14 @@ MF_API int mf_solve(mf_handle_t *h);
  * flow as excess at its tail and deficit at its head), pushes any residual
  * capacity left on arcs out of s, and resumes the loop from the previous
  * state with deficient vertices as extra sinks.
- * Requires a solved handle (MF_ESTATE otherwise).  k == 0 is allowed.
+ * Requires a solved handle (MF_ESTATE otherwise).  k == 0 is allowed.  The
+ * batch is uploaded with one copy through the handle's own device and pinned
+ * staging buffers; they start at min(m, 2^17) updates and double when a batch
+ * does not fit, so only such a batch allocates (mf_apply_updates_noalloc
+ * never does).
  * Errors: MF_EINVAL (id out of range, duplicate id, capacity out of range;
- * the handle is then unchanged), MF_ESTATE, MF_ETIMEOUT, MF_EDEVICE. */
+ * the handle is then unchanged), MF_ESTATE, MF_ETIMEOUT, MF_EDEVICE, MF_ENOMEM
+ * (staging buffers). */
 MF_API int mf_apply_updates(mf_handle_t *h, const int64_t *edge_ids, const int32_t *new_caps,
                             int64_t k);
 
