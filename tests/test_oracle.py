@@ -211,3 +211,58 @@ def test_bfs_heights_match_library_shortest_paths(seed):
     expect = np.where(np.isinf(d), n, d - 1).astype(np.int64)
     expect[pg.s] = n
     assert np.array_equal(h.astype(np.int64), expect)
+
+
+def _relabel(g, new_of_old):
+    """g with vertex v renamed new_of_old[v] (edge i keeps its capacity and
+    becomes edge eid[i] of the relabelled CSR)."""
+    tails = g.tails()
+    nt = new_of_old[tails].astype(np.int64)
+    nh = new_of_old[g.col].astype(np.int64)
+    order = np.argsort((nt << 32) | nh, kind="stable")
+    eid = np.empty(g.m, dtype=np.int64)
+    eid[order] = np.arange(g.m)
+    row_ptr = np.zeros(g.n + 1, dtype=np.int64)
+    np.cumsum(np.bincount(nt, minlength=g.n), out=row_ptr[1:])
+    h = W.Graph(g.n, row_ptr, nh[order].astype(np.int32), g.cap[order].copy(), int(new_of_old[g.s]),
+                int(new_of_old[g.t]))
+    return h, eid
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_relabelling_maps_value_cut_and_heights(seed):
+    """A handle may number the vertices in another order inside (by falling
+    degree, say) and map its results back: what makes that exact is that a
+    relabelling leaves the maximum-flow value unchanged and maps the canonical
+    cut (the vertices that cannot reach t in the residual graph) and the exact
+    BFS heights through the permutation.  Checked with Dinic on random graphs
+    (parallel and antiparallel edges, self-loops), under the degree order the
+    device build uses and under random orders, before and after a batch."""
+    rng = np.random.default_rng(seed)
+    g = tiny_random(seed, n_hi=30, m_hi=120)
+    deg = np.diff(g.row_ptr) + np.bincount(g.col, minlength=g.n)
+    orders = [np.argsort(-deg, kind="stable"), rng.permutation(g.n)]
+    v0, side0, _ = O.dinic(g, g.cap)
+    ids = rng.choice(g.m, max(1, g.m // 4), replace=False).astype(np.int64) if g.m else np.zeros(0, np.int64)
+    new = rng.integers(0, 15, ids.shape[0]).astype(np.int32)
+    cap1 = g.cap.copy()
+    cap1[ids] = new
+    v1, side1, _ = O.dinic(g, cap1)
+    pg = O.PairGraph.build(g, g.cap)
+    for order in orders:
+        new_of_old = np.empty(g.n, dtype=np.int64)
+        new_of_old[order] = np.arange(g.n)
+        h, eid = _relabel(g, new_of_old)
+        w0, hside0, _ = O.dinic(h, h.cap)
+        assert w0 == v0
+        assert np.array_equal(hside0[new_of_old], side0)
+        hcap1 = h.cap.copy()
+        hcap1[eid[ids]] = new
+        w1, hside1, _ = O.dinic(h, hcap1)
+        assert w1 == v1
+        assert np.array_equal(hside1[new_of_old], side1)
+        # exact global-relabel heights of the initial residual state map the same way
+        hp = O.PairGraph.build(h, h.cap)
+        e0 = np.zeros(g.n, dtype=np.int64)
+        assert np.array_equal(O.bfs_heights(hp, hp.cap.copy(), e0)[new_of_old],
+                              O.bfs_heights(pg, pg.cap.copy(), e0))
